@@ -1,0 +1,298 @@
+/*
+ * CPU FP64 oracle for the QR path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The GPU product path shares no code with it.
+ *
+ * What it computes: the thin QR factorisation A = QR of an m x n matrix,
+ * m >= n, by conventional Householder reduction.  In the paper's terms this
+ * is the "trivial tree" (one reduction node holding every row), which the
+ * paper states is conventional Householder QR (Sec. 2.1, the trivial-tree
+ * picture following Eq. TSQR_binarytree_4).  Every TSQR tree and CAQR reach
+ * the same factorisation in exact arithmetic, up to the signs of diag(R)
+ * (Sec. 2.1, uniqueness remark after Eq. TSQR_binarytree_4), so this is the
+ * plain definition the GPU path is compared against.
+ *
+ * Conventions (readings of the paper, see the design notes):
+ *  - Householder vectors have unit topmost nonzero entry, H = I - tau v v^T
+ *    (Sec. 5.2, the normalisation used for the dependency argument).
+ *  - beta = -sign(alpha) * ||x||, with sign(0) = +1; tau = 0 (no reflection)
+ *    when the tail below the diagonal is exactly zero.
+ *  - Every reduction over rows uses pairwise summation.
+ *
+ * Storage: the public entry points take row-major, contiguous arrays (C order,
+ * as numpy stores them).  Internally the factorisation works on a
+ * column-major copy so that columns are contiguous.
+ *
+ * Functions without an independent pin are marked "parity unpinned" in their
+ * comment; at present every exported function is pinned by the CPU tests.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Pairwise (cascade) summation of x[0..n): split in halves down to blocks of
+ * at most 8 terms which are summed left to right. */
+static double psum(const double *x, int64_t n)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            s += x[i];
+        return s;
+    }
+    int64_t h = n / 2;
+    return psum(x, h) + psum(x + h, n - h);
+}
+
+/* Scratch buffer for products fed to psum. */
+typedef struct {
+    double *p;
+    int64_t cap;
+} scratch_t;
+
+static int scratch_reserve(scratch_t *s, int64_t n)
+{
+    if (n <= s->cap)
+        return 0;
+    free(s->p);
+    s->p = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    s->cap = s->p ? n : 0;
+    return s->p ? 0 : -1;
+}
+
+/* sum_i a[i]*b[i] with pairwise summation of the products */
+static double pdot(scratch_t *s, const double *a, const double *b, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        s->p[i] = a[i] * b[i];
+    return psum(s->p, n);
+}
+
+/* Householder QR of a column-major m x n matrix (leading dimension m).
+ * On exit: R on and above the diagonal, v(1:) below it (v(0) = 1 implicit),
+ * tau[j] per column.  Returns 0, or -1 on allocation failure. */
+static int geqr2_cm(int64_t m, int64_t n, double *a, double *tau)
+{
+    scratch_t s = {0, 0};
+    if (scratch_reserve(&s, m) != 0)
+        return -1;
+    for (int64_t j = 0; j < n && j < m; ++j) {
+        double *x = a + j * m + j; /* column j, rows j..m-1 */
+        int64_t len = m - j;
+        double alpha = x[0];
+        double sigma2 = (len > 1) ? pdot(&s, x + 1, x + 1, len - 1) : 0.0;
+        if (sigma2 == 0.0) {
+            /* no reflection: H_j = I, R_jj = alpha, tail already zero */
+            tau[j] = 0.0;
+        } else {
+            double nrm = hypot(alpha, sqrt(sigma2));
+            double beta = (alpha >= 0.0) ? -nrm : nrm; /* sign(0) = +1 */
+            tau[j] = (beta - alpha) / beta;
+            double scale = 1.0 / (alpha - beta);
+            for (int64_t i = 1; i < len; ++i)
+                x[i] *= scale;
+            x[0] = beta;
+        }
+        if (tau[j] == 0.0)
+            continue;
+        /* apply H_j = I - tau v v^T to columns k > j, rows j..m-1 */
+        for (int64_t k = j + 1; k < n; ++k) {
+            double *c = a + k * m + j;
+            /* w = v^T c with v(0) = 1 */
+            s.p[0] = c[0];
+            for (int64_t i = 1; i < len; ++i)
+                s.p[i] = x[i] * c[i];
+            double w = psum(s.p, len);
+            double tw = tau[j] * w;
+            c[0] -= tw;
+            for (int64_t i = 1; i < len; ++i)
+                c[i] -= tw * x[i];
+        }
+    }
+    free(s.p);
+    return 0;
+}
+
+static double *to_cm(int64_t m, int64_t n, const double *rm)
+{
+    double *cm = (double *)malloc((size_t)(m * n > 0 ? m * n : 1) * sizeof(double));
+    if (!cm)
+        return NULL;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            cm[j * m + i] = rm[i * n + j];
+    return cm;
+}
+
+static void from_cm(int64_t m, int64_t n, const double *cm, double *rm)
+{
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            rm[i * n + j] = cm[j * m + i];
+}
+
+/* Householder QR, row-major in place (LAPACK xGEQR2 output layout).
+ * A: m x n row-major.  On exit R is in the upper triangle and the reflector
+ * tails v(1:) are below the diagonal.  tau: n entries.
+ * Returns 0, -1 for bad sizes, -2 on allocation failure. */
+int oracle_geqrf(int64_t m, int64_t n, double *A, double *tau)
+{
+    if (m < 0 || n < 0 || m < n)
+        return -1;
+    double *cm = to_cm(m, n, A);
+    if (!cm)
+        return -2;
+    int rc = geqr2_cm(m, n, cm, tau);
+    from_cm(m, n, cm, A);
+    free(cm);
+    return rc == 0 ? 0 : -2;
+}
+
+/* Apply H_j = I - tau_j v_j v_j^T for j in order (first..last step dir) to the
+ * m x k row-major B, where v_j comes from the geqrf output YR (m x n). */
+static int apply_reflectors(int64_t m, int64_t n, int64_t k, const double *YR,
+                            const double *tau, double *B, int forward)
+{
+    if (m < 0 || n < 0 || k < 0 || m < n)
+        return -1;
+    double *bc = to_cm(m, k, B);
+    double *yc = to_cm(m, n, YR);
+    scratch_t s = {0, 0};
+    if (!bc || !yc || scratch_reserve(&s, m) != 0) {
+        free(bc);
+        free(yc);
+        free(s.p);
+        return -2;
+    }
+    for (int64_t step = 0; step < n; ++step) {
+        int64_t j = forward ? step : n - 1 - step;
+        if (tau[j] == 0.0)
+            continue;
+        const double *v = yc + j * m + j; /* v(0)=1 implicit, v(1:) stored */
+        int64_t len = m - j;
+        for (int64_t c = 0; c < k; ++c) {
+            double *b = bc + c * m + j;
+            s.p[0] = b[0];
+            for (int64_t i = 1; i < len; ++i)
+                s.p[i] = v[i] * b[i];
+            double tw = tau[j] * psum(s.p, len);
+            b[0] -= tw;
+            for (int64_t i = 1; i < len; ++i)
+                b[i] -= tw * v[i];
+        }
+    }
+    from_cm(m, k, bc, B);
+    free(bc);
+    free(yc);
+    free(s.p);
+    return 0;
+}
+
+/* B (m x k) <- Q^T B, Q = H_0 H_1 ... H_{n-1} (so Q^T applies H_0 first). */
+int oracle_apply_qt(int64_t m, int64_t n, int64_t k, const double *YR,
+                    const double *tau, double *B)
+{
+    return apply_reflectors(m, n, k, YR, tau, B, 1);
+}
+
+/* B (m x k) <- Q B (H_{n-1} first). */
+int oracle_apply_q(int64_t m, int64_t n, int64_t k, const double *YR,
+                   const double *tau, double *B)
+{
+    return apply_reflectors(m, n, k, YR, tau, B, 0);
+}
+
+/* Thin Q (m x n, row-major) = Q [I_n; 0]. */
+int oracle_form_q(int64_t m, int64_t n, const double *YR, const double *tau,
+                  double *Q)
+{
+    if (m < 0 || n < 0 || m < n)
+        return -1;
+    memset(Q, 0, (size_t)(m * n) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        Q[i * n + i] = 1.0;
+    return apply_reflectors(m, n, n, YR, tau, Q, 0);
+}
+
+/*
+ * Adjoint (reverse-mode derivative) of the thin QR map A -> (Q, R) with the
+ * normalisation diag(R) > 0.  Not in the paper; this is the published QR
+ * adjoint (Walter & Lehmann; the "copyltu" form of Liao, Liu, Wang & Xiang):
+ *     M    = R * triu(dR)^T - dQ^T * Q                     (n x n)
+ *     C    = tril(M) + tril(M, -1)^T                       (copyltu)
+ *     dA   = (dQ + Q * C) * R^{-T}
+ * Inputs (row-major): Q m x n, R n x n (upper, positive diagonal), dQ m x n,
+ * dR n x n (only its upper triangle is used).  Output dA m x n.
+ * Sums over the m rows are pairwise; the triangular solve is plain
+ * substitution, row by row.
+ */
+int oracle_qr_adjoint(int64_t m, int64_t n, const double *Q, const double *R,
+                      const double *dQ, const double *dR, double *dA)
+{
+    if (m < 0 || n < 0 || m < n)
+        return -1;
+    double *Mx = (double *)calloc((size_t)(n * n > 0 ? n * n : 1), sizeof(double));
+    double *qc = to_cm(m, n, Q);
+    double *dqc = to_cm(m, n, dQ);
+    scratch_t s = {0, 0};
+    if (!Mx || !qc || !dqc || scratch_reserve(&s, m > n ? m : n) != 0) {
+        free(Mx);
+        free(qc);
+        free(dqc);
+        free(s.p);
+        return -2;
+    }
+    /* M = R triu(dR)^T - dQ^T Q */
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            /* (R triu(dR)^T)_{ij} = sum_l R[i][l] * triu(dR)[j][l] */
+            for (int64_t l = 0; l < n; ++l) {
+                double r = (l >= i) ? R[i * n + l] : 0.0;
+                double d = (l >= j) ? dR[j * n + l] : 0.0;
+                acc += r * d;
+            }
+            double g = pdot(&s, dqc + i * m, qc + j * m, m);
+            Mx[i * n + j] = acc - g;
+        }
+    }
+    /* C = copyltu(M): lower triangle kept, mirrored to the upper one */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j)
+            Mx[i * n + j] = Mx[j * n + i];
+    /* Bm = dQ + Q C ; then dA = Bm R^{-T}, i.e. each row x solves R x^T = b^T */
+    double *b = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!b) {
+        free(Mx);
+        free(qc);
+        free(dqc);
+        free(s.p);
+        return -2;
+    }
+    for (int64_t r = 0; r < m; ++r) {
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = dQ[r * n + j];
+            for (int64_t l = 0; l < n; ++l)
+                acc += Q[r * n + l] * Mx[l * n + j];
+            b[j] = acc;
+        }
+        /* back substitution: R x = b, R upper triangular */
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double acc = b[i];
+            for (int64_t l = i + 1; l < n; ++l)
+                acc -= R[i * n + l] * dA[r * n + l];
+            dA[r * n + i] = acc / R[i * n + i];
+        }
+    }
+    free(b);
+    free(Mx);
+    free(qc);
+    free(dqc);
+    free(s.p);
+    return 0;
+}
+
+/* Exposed for the tests: pairwise sum of n doubles. */
+double oracle_psum(const double *x, int64_t n) { return psum(x, n); }
