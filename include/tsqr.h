@@ -1,0 +1,138 @@
+/*
+ * tsqr.h -- C ABI of the MI355X (gfx950) TSQR / CAQR library (libtsqr.so).
+ *
+ * Method: Demmel, Grigori, Hoemmen, Langou, "Communication-optimal parallel
+ * and sequential QR and LU factorizations" (arXiv 0808.2664).
+ *   - TSQR: QR of a tall-skinny m x n matrix (m >= n) as a reduction of
+ *     stacked R factors over a tree (Sec. 2.1, Eqs. TSQR_binarytree_1..4);
+ *     the Q factor is kept as the implicit "tree of Q factors" and never
+ *     multiplied out (Sec. 2.1, remark after Eq. TSQR_binarytree_4).
+ *   - CAQR: right-looking QR whose panel factorisation is TSQR, followed by
+ *     the tree-structured trailing update (Sec. 3 and 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are dense, ROW-MAJOR, with an explicit leading dimension
+ *     counted in elements (ld >= number of columns).
+ *   - Matrix pointers are DEVICE pointers (memory from hipMalloc or a torch
+ *     CUDA/HIP tensor) unless the argument says "host".
+ *   - `stream` is a hipStream_t passed as a plain pointer (NULL = the null
+ *     stream).  Every call is stream-ordered and asynchronous: it enqueues
+ *     work and returns; results are valid once the stream reaches that point.
+ *   - dtype: TSQR_F32 or TSQR_F64.
+ *   - Householder convention: reflectors H = I - tau v v^T with unit topmost
+ *     entry (Sec. 5.2); beta = -sign(alpha)*||x|| with sign(0) = +1, tau = 0
+ *     when the part below the diagonal is already zero.  diag(R) may
+ *     therefore be negative; tsqr_sign_normalize gives diag(R) >= 0.
+ *
+ * Return codes (LAPACK "info" style)
+ *    0                  success
+ *   -i                  argument i (1-based) is invalid; nothing was enqueued
+ *    TSQR_ERR_HIP       a HIP runtime call failed (tsqr_last_hip_error)
+ *    TSQR_ERR_NOMEM     device workspace allocation failed
+ *    TSQR_ERR_PLAN      handle / shape mismatch
+ *    TSQR_ERR_UNSUPPORTED  n > 64 for TSQR, or an unsupported option
+ * NaN/Inf inputs are not detected; they propagate to the outputs.
+ */
+#ifndef TSQR_H
+#define TSQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQR_F32 0
+#define TSQR_F64 1
+
+#define TSQR_SUCCESS 0
+#define TSQR_ERR_HIP 1
+#define TSQR_ERR_NOMEM 2
+#define TSQR_ERR_PLAN 3
+#define TSQR_ERR_UNSUPPORTED 4
+
+#define TSQR_MAX_N 64
+
+/* Opaque implicit Q (the tree of Q factors). */
+typedef struct tsqr_qtree_s* tsqr_qtree;
+
+/* Tree shape.  0 in any field = the library default.
+ *   block_rows : rows per block of the chain kernels: 64, 128 or 256
+ *                (default 256).  Each block's reflectors carry one n x n T.
+ *   chains     : number of contiguous row ranges reduced independently with
+ *                the flat tree of sequential TSQR (Sec. 2.1); their R
+ *                factors are then reduced on the tree.  Default:
+ *                min(number of blocks, 512).  chains = number of blocks gives
+ *                the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
+ *   arity      : fan-in of the tree over the chain R factors (default 2).
+ *   flags      : reserved, must be 0. */
+typedef struct tsqr_opts {
+    int32_t block_rows;
+    int32_t chains;
+    int32_t arity;
+    int32_t flags;
+} tsqr_opts;
+
+/* TSQR factorisation A = QR (Sec. 2.1).
+ *   dtype, m, n (m >= n >= 1, n <= 64), A (device, m x n, lda >= n).
+ *   A is OVERWRITTEN with the reflectors of the tree's leaves (in place,
+ *   like LAPACK xGEQRF); the implicit Q borrows A, so A must stay alive and
+ *   unmodified until tsqr_qtree_destroy.
+ *   R: device n x n (ldr >= n) receives R (upper triangle; zeros below), or
+ *   NULL.  q_out: receives the implicit Q, or NULL (then the tree workspace
+ *   is released at the end of the stream work).
+ *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 R, 7 ldr,
+ *   8 opts, 9 q_out. */
+int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
+/* B <- Q^T B for the full m x m orthogonal Q (Sec. 1: apply the stored tree
+ * of Q factors; "about the same cost as the traditionally represented Q").
+ * B: device m x k (ldb >= k), in place.  Rows 0..n-1 then hold the thin
+ * Q^T B (to the signs of diag R); rows n..m-1 depend on the tree shape.
+ * Errors: 1 q, 2 k, 3 B, 4 ldb. */
+int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
+
+/* B <- Q B (reverse order of tsqr_apply_qt).  Same arguments. */
+int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
+
+/* Thin Q = Q [I_n; 0] (m x n, device, ldq >= n) (Sec. 2.1: Q factors with
+ * n columns).  Errors: 1 q, 2 Q, 3 ldq. */
+int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream);
+
+/* Release the implicit Q (device workspace freed stream-ordered on the
+ * stream of its creation).  NULL is accepted. */
+int tsqr_qtree_destroy(tsqr_qtree q);
+
+/* Host query of a handle: info[0..9] = m, n, block_rows, chains, arity,
+ * levels, blocks, dtype, kind (0 TSQR, 1 CAQR), panel (CAQR).  info: host
+ * array of 10. */
+int tsqr_qtree_info(tsqr_qtree q, int64_t* info);
+
+/* Geometry the library would use for (m, n, opts), without any GPU work.
+ * out (host, 7): block_rows, rows per chain, chains, arity, levels, blocks,
+ * padded width.  Errors: 1 m, 2 n, 3 opts, 4 out. */
+int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out);
+
+/* D = sign(diag R) with sign(0) = +1; R <- D R and Q <- Q D, so diag(R) >= 0
+ * (the QR factorisation is unique up to these signs, Sec. 2.1).
+ * Q: device m x n (ldq >= n) or NULL; R: device n x n (ldr >= n). */
+int tsqr_sign_normalize(int dtype, int64_t m, int64_t n, void* Q, int64_t ldq, void* R, int64_t ldr,
+                        void* stream);
+
+/* Profiling hook.  When start/stop are hipEvent_t handles (plain pointers),
+ * every later call records them on its stream right before and right after
+ * the chain (leaf) kernel of `phase`: 0 tsqr_factor, 1 tsqr_apply_qt,
+ * 2 tsqr_apply_q, 3 tsqr_form_q.  NULL disables.  Process-wide; not thread
+ * safe.  Errors: 1 phase. */
+int tsqr_set_phase_events(int phase, void* start, void* stop);
+
+/* Last HIP error code seen by this thread (0 if none) and a message. */
+int tsqr_last_hip_error(void);
+const char* tsqr_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H */

@@ -1,0 +1,9 @@
+"""MI355X-native TSQR / CAQR (Demmel, Grigori, Hoemmen, Langou, arXiv 0808.2664).
+
+The compute path is libtsqr.so (hand-written HIP kernels for gfx950, C ABI in
+include/tsqr.h); this package is the thin Python binding over it.
+"""
+from .tsqr import QTree, factor, plan_geometry, qr, sign_normalize  # noqa: F401
+from . import _lib  # noqa: F401
+
+__all__ = ["QTree", "factor", "plan_geometry", "qr", "sign_normalize"]

@@ -1,0 +1,346 @@
+// C ABI of libtsqr.so: argument checks, tree geometry, workspace and the
+// launch sequences of TSQR (Sec. 2.1) and its implicit Q.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/tsqr.h"
+#include "tsqr_common.hpp"
+
+using tsqr::Geom;
+using tsqr::Work;
+
+struct tsqr_qtree_s {
+    int kind = 0;  // 0 TSQR, 1 CAQR
+    bool f64 = true;
+    Geom g;
+    void* A = nullptr;  // borrowed reflector storage
+    int64_t lda = 0;
+    Work wk;
+    hipStream_t stream = nullptr;
+    // CAQR: one TSQR tree per panel, panel p acting on rows/cols p*panel..
+    std::vector<tsqr_qtree_s*> panels;
+    int64_t m = 0, n = 0, panel = 0;
+};
+
+static thread_local int g_last_hip = 0;
+
+namespace tsqr {
+PhaseEvents g_phase;
+}
+
+static int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? TSQR_ERR_NOMEM : TSQR_ERR_HIP;
+}
+
+static int env_int(const char* name, int dflt) {
+    const char* s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+namespace tsqr {
+
+int padded_nc(int64_t n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64; }
+
+// Tree geometry for (m, n): chains of whole blocks, the last chain absorbing
+// a remainder too short to hold an n x n leaf (a chain's first block must hold
+// n rows: its R is an n x n triangle).
+int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
+    if (n < 1 || n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (m < n) return -1;
+    int h = (o && o->block_rows) ? o->block_rows : env_int("TSQR_BLOCK_ROWS", 256);
+    int chains = (o && o->chains) ? o->chains : env_int("TSQR_CHAINS", 0);
+    int arity = (o && o->arity) ? o->arity : env_int("TSQR_ARITY", 2);
+    if (o && o->flags != 0) return TSQR_ERR_UNSUPPORTED;
+    if (h != 64 && h != 128 && h != 256) return TSQR_ERR_UNSUPPORTED;
+    if (arity < 2 || chains < 0) return TSQR_ERR_UNSUPPORTED;
+    const int64_t blocks_total = (m + h - 1) / h;
+    int64_t W0 = chains > 0 ? chains : (blocks_total < 512 ? blocks_total : 512);
+    if (W0 < 1) W0 = 1;
+    if (W0 > blocks_total) W0 = blocks_total;
+    int64_t per = (m + W0 - 1) / W0;               // rows per chain before rounding
+    int64_t S = ((per + h - 1) / h) * h;           // whole blocks
+    int64_t W = (m + S - 1) / S;
+    if (W > 1 && m - (W - 1) * S < n) W -= 1;      // merge a too-short last chain
+    if (W > 0x7fffffff) return TSQR_ERR_UNSUPPORTED;
+    g->m = m;
+    g->n = n;
+    g->h = h;
+    g->S = S;
+    g->W = (int)W;
+    g->arity = arity;
+    int levels = 0;
+    int64_t stride = 1;
+    while (stride < W) {
+        stride *= arity;
+        ++levels;
+    }
+    g->levels = levels;
+    const int64_t last = m - (W - 1) * S;
+    g->nblocks = (W - 1) * (S / h) + (last + h - 1) / h;
+    g->NC = padded_nc(n);
+    return 0;
+}
+
+size_t work_bytes(const Geom& g, bool f64) {
+    const size_t es = f64 ? 8 : 4;
+    const size_t n = (size_t)g.n, tri = n * (n + 1) / 2;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + 3 * al((size_t)g.W * n * n * es) +
+           al((size_t)g.W * tri * es) + al((size_t)g.W * n * es);
+}
+
+void work_carve(Work* w, const Geom& g, bool f64) {
+    const size_t es = f64 ? 8 : 4;
+    const size_t n = (size_t)g.n, tri = n * (n + 1) / 2;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char* p = (char*)w->base;
+    w->tau_blk = p;
+    p += al(g.nblocks * n * es);
+    w->T_blk = p;
+    p += al(g.nblocks * tri * es);
+    w->Rbuf = p;
+    p += al((size_t)g.W * n * n * es);
+    w->Ynode = p;
+    p += al((size_t)g.W * n * n * es);
+    w->Tnode = p;
+    p += al((size_t)g.W * tri * es);
+    w->tau_node = p;
+    p += al((size_t)g.W * n * es);
+    // third n*n*W slot: scratch (unused slot kept so layouts stay aligned)
+}
+
+}  // namespace tsqr
+
+// ------------------------------------------------------------------ helpers
+
+static int check_dtype(int dtype) { return dtype == TSQR_F32 || dtype == TSQR_F64; }
+
+// TSQR of a device matrix into a fresh handle (shared by tsqr_factor and the
+// CAQR panels).  R: optional; r_upper_only keeps what is below R's diagonal.
+static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                       bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st) {
+    Geom g;
+    int rc = tsqr::make_geom(m, n, opts, &g);
+    if (rc != 0) return rc;
+    const bool f64 = dtype == TSQR_F64;
+    tsqr_qtree_s* q = new tsqr_qtree_s();
+    q->kind = 0;
+    q->f64 = f64;
+    q->g = g;
+    q->A = A;
+    q->lda = lda;
+    q->stream = st;
+    q->m = m;
+    q->n = n;
+    q->wk.bytes = tsqr::work_bytes(g, f64);
+    hipError_t e = hipMallocAsync(&q->wk.base, q->wk.bytes, st);
+    if (e != hipSuccess) {
+        delete q;
+        return hip_fail(e);
+    }
+    tsqr::work_carve(&q->wk, g, f64);
+    e = tsqr::launch_factor(f64, g, A, lda, q->wk, st);
+    if (e == hipSuccess && R) e = tsqr::launch_copy_r(f64, n, q->wk.Rbuf, R, ldr, !r_upper_only, st);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(q->wk.base, st);
+        delete q;
+        return hip_fail(e);
+    }
+    *out = q;
+    return 0;
+}
+
+static void destroy_impl(tsqr_qtree_s* q) {
+    if (!q) return;
+    for (auto* p : q->panels) destroy_impl(p);
+    if (q->wk.base) (void)hipFreeAsync(q->wk.base, q->stream);
+    delete q;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                const tsqr_opts* opts, tsqr_qtree* q_out, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (R && ldr < n) return -7;
+    if (opts && (opts->flags != 0)) return -8;
+    if (!R && !q_out) return -9;
+    tsqr_qtree_s* q = nullptr;
+    int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream);
+    if (rc != 0) return rc == -1 ? -2 : rc;
+    if (q_out) *q_out = q;
+    else destroy_impl(q);
+    return 0;
+}
+
+static int apply_impl(tsqr_qtree_s* q, int64_t k, void* B, int64_t ldb, int mode, hipStream_t st);
+
+static int apply_one(tsqr_qtree_s* q, int64_t k, void* B, int64_t ldb, int mode, bool compute_f64,
+                     hipStream_t st) {
+    hipError_t e = tsqr::launch_apply(q->f64, compute_f64, q->g, q->A, q->lda, q->wk, B, ldb, k, mode, st);
+    return e == hipSuccess ? 0 : hip_fail(e);
+}
+
+// CAQR: Q = Q_0 Q_1 ... Q_{P-1}, panel p acting on rows p*b .. m-1.
+static int apply_impl(tsqr_qtree_s* q, int64_t k, void* B, int64_t ldb, int mode, hipStream_t st) {
+    if (q->kind == 0) return apply_one(q, k, B, ldb, mode, q->f64, st);
+    const size_t es = q->f64 ? 8 : 4;
+    const int P = (int)q->panels.size();
+    for (int i = 0; i < P; ++i) {
+        const int p = (mode == tsqr::MODE_QT) ? i : P - 1 - i;
+        char* Bp = (char*)B + (size_t)p * q->panel * ldb * es;
+        int rc = apply_one(q->panels[p], k, Bp, ldb, mode == tsqr::MODE_FORMQ ? tsqr::MODE_Q : mode, q->f64, st);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
+    if (!q) return -1;
+    if (k < 0) return -2;
+    if (k == 0) return 0;
+    if (!B) return -3;
+    if (ldb < k) return -4;
+    return apply_impl(q, k, B, ldb, tsqr::MODE_QT, (hipStream_t)stream);
+}
+
+int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
+    if (!q) return -1;
+    if (k < 0) return -2;
+    if (k == 0) return 0;
+    if (!B) return -3;
+    if (ldb < k) return -4;
+    return apply_impl(q, k, B, ldb, tsqr::MODE_Q, (hipStream_t)stream);
+}
+
+int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
+    if (!q) return -1;
+    if (!Q) return -2;
+    if (ldq < q->n) return -3;
+    hipStream_t st = (hipStream_t)stream;
+    if (q->kind != 0) return TSQR_ERR_UNSUPPORTED;
+    hipError_t e = tsqr::launch_init_formq(q->f64, q->n, Q, ldq, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return apply_one(q, q->n, Q, ldq, tsqr::MODE_FORMQ, q->f64, st);
+}
+
+int tsqr_qtree_destroy(tsqr_qtree q) {
+    destroy_impl(q);
+    return 0;
+}
+
+int tsqr_qtree_info(tsqr_qtree q, int64_t* info) {
+    if (!q) return -1;
+    if (!info) return -2;
+    info[0] = q->m;
+    info[1] = q->n;
+    info[2] = q->g.h;
+    info[3] = q->g.W;
+    info[4] = q->g.arity;
+    info[5] = q->g.levels;
+    info[6] = q->g.nblocks;
+    info[7] = q->f64 ? TSQR_F64 : TSQR_F32;
+    info[8] = q->kind;
+    info[9] = q->panel;
+    return 0;
+}
+
+int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out) {
+    if (m < 1) return -1;
+    if (n < 1 || n > m) return n > m ? -1 : -2;
+    if (!out) return -4;
+    Geom g;
+    int rc = tsqr::make_geom(m, n, opts, &g);
+    if (rc == -1) return -1;
+    if (rc != 0) return rc;
+    out[0] = g.h;
+    out[1] = g.S;
+    out[2] = g.W;
+    out[3] = g.arity;
+    out[4] = g.levels;
+    out[5] = g.nblocks;
+    out[6] = g.NC;
+    return 0;
+}
+
+int tsqr_last_hip_error(void) { return g_last_hip; }
+
+int tsqr_set_phase_events(int phase, void* start, void* stop) {
+    if (phase < 0 || phase >= tsqr::NPHASE) return -1;
+    tsqr::g_phase.start[phase] = (hipEvent_t)start;
+    tsqr::g_phase.stop[phase] = (hipEvent_t)stop;
+    return 0;
+}
+
+const char* tsqr_status_string(int status) {
+    switch (status) {
+        case TSQR_SUCCESS: return "success";
+        case TSQR_ERR_HIP: return "HIP runtime error";
+        case TSQR_ERR_NOMEM: return "device memory allocation failed";
+        case TSQR_ERR_PLAN: return "handle or shape mismatch";
+        case TSQR_ERR_UNSUPPORTED: return "unsupported size or option";
+        default: return status < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ sign normalisation
+
+template <typename T>
+__global__ void k_sign_normalize(int64_t m, int64_t n, T* __restrict__ Q, int64_t ldq, T* __restrict__ R,
+                                 int64_t ldr) {
+    // one pass over R (rows) and Q (all rows); d_j = -1 if R_jj < 0 else +1
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t totq = Q ? m * n : 0;
+    if (e < totq) {
+        const int64_t i = e / n, j = e - i * n;
+        if (R[j * ldr + j] < T(0)) Q[i * ldq + j] = -Q[i * ldq + j];
+    }
+}
+
+template <typename T>
+__global__ void k_sign_normalize_r(int64_t n, T* __restrict__ R, int64_t ldr) {
+    // row i of R scaled by d_i; each workgroup owns one row and reads R_ii first
+    const int64_t i = blockIdx.x;
+    const T d = (R[i * ldr + i] < T(0)) ? T(-1) : T(1);
+    __syncthreads();
+    for (int64_t j = i + threadIdx.x; j < n; j += blockDim.x) R[i * ldr + j] *= d;
+}
+
+extern "C" int tsqr_sign_normalize(int dtype, int64_t m, int64_t n, void* Q, int64_t ldq, void* R, int64_t ldr,
+                                   void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 0) return -2;
+    if (n < 0 || (Q && n > m)) return -3;
+    if (Q && ldq < n) return -5;
+    if (!R) return -6;
+    if (ldr < n) return -7;
+    if (n == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t totq = Q ? m * n : 0;
+    if (totq > 0) {
+        const int64_t nb = (totq + 255) / 256;
+        if (dtype == TSQR_F64)
+            k_sign_normalize<double><<<(unsigned)nb, 256, 0, st>>>(m, n, (double*)Q, ldq, (double*)R, ldr);
+        else
+            k_sign_normalize<float><<<(unsigned)nb, 256, 0, st>>>(m, n, (float*)Q, ldq, (float*)R, ldr);
+    }
+    if (dtype == TSQR_F64)
+        k_sign_normalize_r<double><<<(unsigned)n, 64, 0, st>>>(n, (double*)R, ldr);
+    else
+        k_sign_normalize_r<float><<<(unsigned)n, 64, 0, st>>>(n, (float*)R, ldr);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : hip_fail(e);
+}

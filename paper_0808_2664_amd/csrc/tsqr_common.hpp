@@ -1,0 +1,170 @@
+// Shared host/device definitions of the TSQR library (gfx950).
+//
+// Geometry of one TSQR (paper Sec. 2.1): the m x n matrix is split into W
+// contiguous row ranges ("chains").  Each chain is reduced by one workgroup
+// with the flat tree of sequential TSQR (Sec. 2.1, flat-tree picture): its
+// first block is factored, the R factor stays on chip, and every further block
+// is factored stacked under that R.  The W chain R factors are then reduced on
+// a tree of arity `arity` (binary by default, Eq. TSQR_binarytree_1..4).
+// Any tree gives a valid QR (Sec. 2.1, remark after the flat tree).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsqr {
+
+// ----------------------------------------------------------------- geometry
+struct Geom {
+    int64_t m = 0, n = 0;
+    int h = 0;            // rows per block (tile height of the chain kernel)
+    int64_t S = 0;        // rows per chain, a multiple of h (the last chain differs)
+    int W = 0;            // number of chains
+    int arity = 2;        // tree arity
+    int levels = 0;       // tree levels above the chains
+    int64_t nblocks = 0;  // blocks over all chains
+    int NC = 0;           // padded column count: 8, 16, 32 or 64
+};
+
+__host__ __device__ inline int64_t chain_start(const Geom& g, int c) { return (int64_t)c * g.S; }
+__host__ __device__ inline int64_t chain_end(const Geom& g, int c) {
+    return (c == g.W - 1) ? g.m : (int64_t)(c + 1) * g.S;
+}
+__host__ __device__ inline int chain_nblocks(const Geom& g, int c) {
+    int64_t len = chain_end(g, c) - chain_start(g, c);
+    return (int)((len + g.h - 1) / g.h);
+}
+__host__ __device__ inline int64_t chain_blk0(const Geom& g, int c) { return (int64_t)c * (g.S / g.h); }
+
+// Tree level `lev` (1-based) with arity a: stride = a^(lev-1).  Nodes start at
+// multiples of a*stride; their children are i + t*stride, t = 1..a-1, < W.
+// The step that folds child c into its node is stored in slot c (1 <= c < W).
+__host__ __device__ inline int64_t ipow(int64_t a, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= a;
+    return r;
+}
+
+inline int packed_tri(int n) { return n * (n + 1) / 2; }
+
+// Workspace carried by an implicit Q (the "tree of Q factors", Sec. 2.1).
+struct Work {
+    void* base = nullptr;
+    size_t bytes = 0;
+    void* tau_blk = nullptr;   // nblocks x n
+    void* T_blk = nullptr;     // nblocks x n(n+1)/2, packed upper, column by column
+    void* Rbuf = nullptr;      // W x n x n
+    void* Ynode = nullptr;     // W x n x n  (slot c holds the step folding chain c)
+    void* Tnode = nullptr;     // W x n(n+1)/2
+    void* tau_node = nullptr;  // W x n
+};
+
+enum ApplyMode { MODE_QT = 0, MODE_Q = 1, MODE_FORMQ = 2 };
+
+// Profiling hook: when set, events are recorded on the launch stream right
+// before and after the chain (leaf) kernel of a phase:
+// 0 factor, 1 apply Q^T, 2 apply Q, 3 form Q.
+constexpr int NPHASE = 4;
+struct PhaseEvents {
+    hipEvent_t start[NPHASE] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t stop[NPHASE] = {nullptr, nullptr, nullptr, nullptr};
+};
+extern PhaseEvents g_phase;
+inline void phase_begin(int p, hipStream_t st) {
+    if (g_phase.start[p]) (void)hipEventRecord(g_phase.start[p], st);
+}
+inline void phase_end(int p, hipStream_t st) {
+    if (g_phase.stop[p]) (void)hipEventRecord(g_phase.stop[p], st);
+}
+
+// Launchers (defined in the .hip files).  Return a hipError_t.
+hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, hipStream_t st);
+hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, void* R, int64_t ldr, bool zero_lower,
+                         hipStream_t st);
+hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const void* Y, int64_t ldy,
+                        const Work& wk, void* B, int64_t ldb, int64_t k, int mode, hipStream_t st);
+hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+
+}  // namespace tsqr
+
+#ifdef __HIP_DEVICE_COMPILE__
+#define TSQR_DEVICE 1
+#endif
+
+namespace tsqr {
+namespace dev {
+
+// ---- cross-lane helpers (wave64) ----
+// DPP controls: quad_perm [1,0,3,2] (xor 1), quad_perm [2,3,0,1] (xor 2),
+// row_half_mirror (lane i <-> 7-i within each group of 8).
+constexpr int DPP_XOR1 = 0xB1;
+constexpr int DPP_XOR2 = 0x4E;
+constexpr int DPP_HMIRROR = 0x141;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    int x = __builtin_bit_cast(int, v);
+    x = __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(float, x);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    struct P { int lo, hi; };
+    P p = __builtin_bit_cast(P, v);
+    p.lo = __builtin_amdgcn_update_dpp(0, p.lo, CTRL, 0xF, 0xF, false);
+    p.hi = __builtin_amdgcn_update_dpp(0, p.hi, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, p);
+}
+
+// Sum over the 8 consecutive lanes of a group; every lane of the group gets the
+// same (bitwise) result because each step adds the same two operands.
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+    v += dpp<DPP_XOR1>(v);
+    v += dpp<DPP_XOR2>(v);
+    v += dpp<DPP_HMIRROR>(v);
+    return v;
+}
+
+__device__ __forceinline__ double shfl(double v, int src) {
+    struct P { int lo, hi; };
+    P p = __builtin_bit_cast(P, v);
+    p.lo = __builtin_amdgcn_ds_bpermute(src << 2, p.lo);
+    p.hi = __builtin_amdgcn_ds_bpermute(src << 2, p.hi);
+    return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ float shfl(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+
+// ---- MFMA 16x16x4 (one block) in FP64 and FP32 ----
+// Operand layout (lane l of a wave64):
+//   A (16x4):  A[l % 16][l / 16]
+//   B (4x16):  B[l / 16][l % 16]
+//   D (16x16): FP32: D[4*(l/16) + r][l % 16];  FP64: D[4*r + l/16][l % 16]
+//   (r = 0..3; the FP64 form was confirmed on gfx950 by a lane-layout probe)
+// orow(l/16, r) gives the output row of register r.
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename C>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef d4 acc;
+    __device__ __forceinline__ static acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int orow(int l4, int r) { return 4 * r + l4; }
+};
+template <>
+struct Mfma<float> {
+    typedef f4 acc;
+    __device__ __forceinline__ static acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int orow(int l4, int r) { return 4 * l4 + r; }
+};
+
+}  // namespace dev
+}  // namespace tsqr

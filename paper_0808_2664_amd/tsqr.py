@@ -1,0 +1,150 @@
+"""Python API over the C ABI (torch tensors for device memory and streams).
+
+All arithmetic runs in the HIP kernels of libtsqr.so; this module only passes
+pointers, sizes and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.TSQR_F64
+    if t.dtype == torch.float32:
+        return _lib.TSQR_F32
+    raise TypeError("only float32 and float64 are supported, got %s" % t.dtype)
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda/hip) tensor")
+    if t.stride(1) != 1 and t.size(1) > 1:
+        raise ValueError("expected a row-major tensor (unit column stride)")
+    return max(t.stride(0), t.size(1), 1)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(block_rows=0, chains=0, arity=0):
+    if not (block_rows or chains or arity):
+        return None
+    o = _lib.opts(block_rows, chains, arity)
+    return ctypes.byref(o)
+
+
+def plan_geometry(m: int, n: int, block_rows=0, chains=0, arity=0) -> dict:
+    """Tree geometry for an m x n TSQR (host only, no GPU work)."""
+    lib = _lib.load()
+    out = (ctypes.c_int64 * 7)()
+    _lib.check("tsqr_plan_geometry", lib.tsqr_plan_geometry(m, n, _opts(block_rows, chains, arity), out))
+    keys = ("block_rows", "chain_rows", "chains", "arity", "levels", "blocks", "padded_n")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+class QTree:
+    """Implicit Q of a TSQR (or CAQR) factorisation: the tree of Q factors."""
+
+    def __init__(self, handle: ctypes.c_void_p, A: torch.Tensor, m: int, n: int):
+        self._h = handle
+        self._A = A  # the reflectors live in A's storage
+        self.m = m
+        self.n = n
+        self.dtype = A.dtype
+        self.device = A.device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 10)()
+        _lib.check("tsqr_qtree_info", _lib.load().tsqr_qtree_info(self._h, out))
+        keys = ("m", "n", "block_rows", "chains", "arity", "levels", "blocks", "dtype", "kind", "panel")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def _check_b(self, B: torch.Tensor):
+        if B.dtype != self.dtype or B.device != self.device:
+            raise ValueError("B must match the factor's dtype and device")
+        if B.dim() != 2 or B.size(0) != self.m:
+            raise ValueError("B must be %d x k" % self.m)
+
+    def apply_qt(self, B: torch.Tensor) -> torch.Tensor:
+        """B <- Q^T B in place (full m x m Q)."""
+        self._check_b(B)
+        _lib.check("tsqr_apply_qt",
+                   _lib.load().tsqr_apply_qt(self._h, B.size(1), _ptr(B), _ld(B), _stream(B)))
+        return B
+
+    def apply_q(self, B: torch.Tensor) -> torch.Tensor:
+        """B <- Q B in place (full m x m Q)."""
+        self._check_b(B)
+        _lib.check("tsqr_apply_q",
+                   _lib.load().tsqr_apply_q(self._h, B.size(1), _ptr(B), _ld(B), _stream(B)))
+        return B
+
+    def form_q(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Explicit thin Q (m x n)."""
+        Q = out if out is not None else torch.empty(self.m, self.n, dtype=self.dtype, device=self.device)
+        _lib.check("tsqr_form_q", _lib.load().tsqr_form_q(self._h, _ptr(Q), _ld(Q), _stream(Q)))
+        return Q
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().tsqr_qtree_destroy(self._h)
+            self._h = None
+            self._A = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0):
+    """TSQR of A (m x n, m >= n, n <= 64), IN PLACE: A is overwritten by the
+    leaf reflectors.  Returns (R, QTree); diag(R) carries the Householder
+    signs (see sign_normalize)."""
+    lib = _lib.load()
+    m, n = A.shape
+    if R is None:
+        R = torch.empty(n, n, dtype=A.dtype, device=A.device)
+    h = ctypes.c_void_p()
+    rc = lib.tsqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(R), _ld(R),
+                         _opts(block_rows, chains, arity), ctypes.byref(h), _stream(A))
+    _lib.check("tsqr_factor", rc)
+    return R, QTree(h, A, m, n)
+
+
+def sign_normalize(Q: torch.Tensor | None, R: torch.Tensor):
+    """R <- D R, Q <- Q D with D = sign(diag R), sign(0) = +1 (in place)."""
+    lib = _lib.load()
+    n = R.size(0)
+    m = Q.size(0) if Q is not None else n
+    rc = lib.tsqr_sign_normalize(_dtype_code(R), m, n, _ptr(Q) if Q is not None else None,
+                                 _ld(Q) if Q is not None else n, _ptr(R), _ld(R), _stream(R))
+    _lib.check("tsqr_sign_normalize", rc)
+    return Q, R
+
+
+def qr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
+    """Thin QR with diag(R) >= 0; A is not modified.  Returns (Q, R)."""
+    W = A.contiguous().clone()
+    R, qt = factor(W, block_rows=block_rows, chains=chains, arity=arity)
+    Q = qt.form_q()
+    sign_normalize(Q, R)
+    qt.close()
+    return Q, R

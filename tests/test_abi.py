@@ -1,0 +1,117 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/tsqr.h, and rejects invalid arguments before touching
+the device.  Also the host-side tree geometry (Sec. 2.1 trees)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0808_2664_amd import _lib
+from paper_0808_2664_amd.tsqr import plan_geometry
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b((?:tsqr|caqr)_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert "tsqr_factor" in names and "tsqr_apply_qt" in names and "tsqr_form_q" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = _lib.load()
+    assert lib.tsqr_status_string(0) == b"success"
+    assert lib.tsqr_status_string(-3) == b"invalid argument"
+
+
+def test_factor_argument_errors_without_launch():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: every call below fails its checks first
+    h = vp()
+    f = lib.tsqr_factor
+    assert f(7, 100, 4, fake, 4, fake, 4, None, ctypes.byref(h), None) == -1       # dtype
+    assert f(1, 0, 4, fake, 4, fake, 4, None, ctypes.byref(h), None) == -2         # m
+    assert f(1, 3, 4, fake, 4, fake, 4, None, ctypes.byref(h), None) == -2         # m < n
+    assert f(1, 100, 0, fake, 4, fake, 4, None, ctypes.byref(h), None) == -3       # n
+    assert f(1, 100, 65, fake, 65, fake, 65, None, ctypes.byref(h), None) == _lib.TSQR_ERR_UNSUPPORTED
+    assert f(1, 100, 4, None, 4, fake, 4, None, ctypes.byref(h), None) == -4       # A
+    assert f(1, 100, 4, fake, 3, fake, 4, None, ctypes.byref(h), None) == -5       # lda
+    assert f(1, 100, 4, fake, 4, fake, 3, None, ctypes.byref(h), None) == -7       # ldr
+    bad = _lib.opts(flags=1)
+    assert f(1, 100, 4, fake, 4, fake, 4, ctypes.byref(bad), ctypes.byref(h), None) == -8
+    assert f(1, 100, 4, fake, 4, None, 4, None, None, None) == -9                  # nothing to return
+    bad_h = _lib.opts(block_rows=100)
+    assert f(1, 100, 4, fake, 4, fake, 4, ctypes.byref(bad_h), ctypes.byref(h), None) == _lib.TSQR_ERR_UNSUPPORTED
+
+
+def test_apply_argument_errors():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    assert lib.tsqr_apply_qt(None, 4, vp(0x1000), 4, None) == -1
+    assert lib.tsqr_apply_q(None, 4, vp(0x1000), 4, None) == -1
+    assert lib.tsqr_form_q(None, vp(0x1000), 4, None) == -1
+    assert lib.tsqr_qtree_destroy(None) == 0
+    assert lib.tsqr_sign_normalize(5, 10, 4, None, 4, vp(0x1000), 4, None) == -1
+    assert lib.tsqr_sign_normalize(1, 10, 4, None, 4, None, 4, None) == -6
+
+
+@pytest.mark.parametrize("m,n,h,chains,arity", [
+    (4096, 16, 256, 0, 0), (1 << 20, 64, 256, 0, 0), (1000, 8, 64, 0, 3),
+    (300, 64, 256, 0, 0), (64, 64, 64, 0, 0), (129, 64, 64, 0, 0), (10000, 33, 128, 7, 4),
+    (65536 + 17, 32, 128, 100, 2),
+])
+def test_plan_geometry_covers_rows(m, n, h, chains, arity):
+    g = plan_geometry(m, n, block_rows=h, chains=chains, arity=arity)
+    assert g["block_rows"] == h
+    S, W = g["chain_rows"], g["chains"]
+    assert S % h == 0 and W >= 1
+    last = m - (W - 1) * S
+    assert last >= n                      # every chain's first block holds an n x n leaf
+    assert (W - 1) * S < m
+    assert g["blocks"] == (W - 1) * (S // h) + (last + h - 1) // h
+    # tree levels: smallest L with arity^L >= W
+    a = g["arity"]
+    assert a ** g["levels"] >= W and (g["levels"] == 0 or a ** (g["levels"] - 1) < W)
+    assert g["padded_n"] in (8, 16, 32, 64) and g["padded_n"] >= n
+
+
+def test_plan_geometry_config1_is_binary_tree_over_256_row_blocks():
+    g = plan_geometry(4096, 16)
+    assert g["block_rows"] == 256 and g["chains"] == 16 and g["chain_rows"] == 256
+    assert g["arity"] == 2 and g["levels"] == 4
+
+
+def test_plan_geometry_short_last_chain_merges():
+    # 3 chains of 256 rows would leave 10 rows (< n = 16) for a fourth chain
+    g = plan_geometry(3 * 256 + 10, 16, block_rows=256, chains=4)
+    assert g["chains"] == 3
+    assert 3 * 256 + 10 - 2 * g["chain_rows"] >= 16
+
+
+def test_implicit_q_parameter_count():
+    """Sec. 5.2: TSQR stores as many reflector entries as Householder QR,
+    mn - n(n+1)/2, when every leaf is n x n or taller: each leaf stores the
+    below-diagonal part of its block, each tree step an upper triangle of a
+    combined triangle."""
+    for (m, n, h) in [(4096, 16, 256), (1024, 8, 64), (2048, 64, 256)]:
+        g = plan_geometry(m, n, block_rows=h, chains=m // h)
+        W = g["chains"]
+        leaves = W * (h * n - n * (n + 1) // 2)
+        steps = (W - 1) * (n * (n + 1) // 2)
+        assert leaves + steps == m * n - n * (n + 1) // 2

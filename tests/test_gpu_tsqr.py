@@ -1,0 +1,267 @@
+"""GPU parity of TSQR factor / apply_qt / apply_q / form_q against the oracle.
+
+Gates (FP64, cond <= 1e8): normwise R error <= 1e-11; residual and
+orthogonality <= 1e-13.  Q and the thin Q^T B are compared at 1e-11 for
+well-conditioned inputs and at 100*cond*u otherwise (a property of the
+problem, not of the algorithm: two correct QRs differ by ~cond*u there).
+Rows n..m-1 of Q^T B depend on the tree; they are checked through their
+column norms (the least-squares residual norms), which do not.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+U64 = np.finfo(np.float64).eps / 2
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype=dtype)
+
+
+def _gram_pairwise(Q, chunk=1024):
+    """Q^T Q with 1024-row chunks summed pairwise: a single GEMM over 2^20 rows
+    has a summation error (~2e-13 on an exactly computed Q) larger than the
+    1e-13 orthogonality gate, so the check itself must sum pairwise."""
+    m, n = Q.shape
+    pad = (-m) % chunk
+    if pad:
+        Q = torch.cat([Q, torch.zeros(pad, n, dtype=Q.dtype, device=Q.device)])
+    Qc = Q.reshape(-1, chunk, n)
+    G = torch.bmm(Qc.transpose(1, 2).contiguous(), Qc)
+    while G.shape[0] > 1:
+        if G.shape[0] % 2:
+            G = torch.cat([G, torch.zeros_like(G[:1])])
+        G = G[0::2] + G[1::2]
+    return G[0]
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(A_np, B_np=None, dtype=torch.float64, **kw):
+    import paper_0808_2664_amd as tq
+    A = _dev(A_np, dtype)
+    R, qt = tq.factor(A, **kw)
+    Q = qt.form_q()
+    out = {"R": R, "Q": Q, "qt": qt, "A": A}
+    if B_np is not None:
+        B = _dev(B_np, dtype)
+        qt.apply_qt(B)
+        out["QtB"] = B.clone()
+        qt.apply_q(B)
+        out["B_back"] = B
+    torch.cuda.synchronize()
+    return out
+
+
+def _normalised(R, Q, QtB=None):
+    R = R.double().cpu().numpy()
+    d = oracle.signs(R)
+    res = {"R": R * d[:, None], "Q": Q.double().cpu().numpy() * d[None, :]}
+    if QtB is not None:
+        X = QtB.double().cpu().numpy()
+        res["thin"] = X[: R.shape[0]] * d[:, None]
+        res["rest_norms"] = np.linalg.norm(X[R.shape[0]:], axis=0)
+    return res
+
+
+def _oracle(A, B=None):
+    YR, tau = oracle.geqrf(A)
+    R = oracle.r_of(YR)
+    Q = oracle.form_q(YR, tau)
+    d = oracle.signs(R)
+    o = {"R": R * d[:, None], "Q": Q * d[None, :]}
+    if B is not None:
+        X = oracle.apply_qt(YR, tau, B)
+        n = A.shape[1]
+        o["thin"] = X[:n] * d[:, None]
+        o["rest_norms"] = np.linalg.norm(X[n:], axis=0)
+    return o
+
+
+def _check(A, B, g, o, rtol_r=1e-11, rtol_q=1e-11, inv=1e-13):
+    assert oracle.rel_err(g["R"], o["R"]) <= rtol_r
+    assert oracle.rel_err(g["Q"], o["Q"]) <= rtol_q
+    assert oracle.residual(A, g["Q"], g["R"]) <= inv
+    assert oracle.orthogonality(g["Q"]) <= inv
+    if B is not None:
+        assert oracle.rel_err(g["thin"], o["thin"]) <= rtol_q
+        np.testing.assert_allclose(g["rest_norms"], o["rest_norms"], rtol=max(rtol_q, 1e-12))
+
+
+def test_config1_4096x16_f64():
+    """4096 x 16, iid N(0,1) (seed 1), row blocks of 256, binary tree."""
+    _note("case: config1 4096x16 f64")
+    A = workloads.cfg1()
+    B = workloads.gaussian(4096, 5, 99)
+    out = _run(A, B, block_rows=256)
+    info = out["qt"].info()
+    assert info["chains"] == 16 and info["levels"] == 4 and info["arity"] == 2
+    g = _normalised(out["R"], out["Q"], out["QtB"])
+    _check(A, B, g, _oracle(A, B))
+    np.testing.assert_allclose(out["B_back"].cpu().numpy(), B, atol=1e-13)
+
+
+SHAPES = [
+    # m, n, block_rows, chains, arity
+    (64, 64, 64, 0, 0),
+    (100, 1, 64, 0, 0),
+    (1000, 3, 64, 0, 0),
+    (1000, 8, 64, 5, 3),
+    (777, 31, 128, 0, 0),
+    (2049, 32, 256, 0, 0),
+    (2500, 33, 128, 3, 2),
+    (5000, 64, 256, 0, 0),
+    (5000, 64, 128, 1, 0),
+    (3333, 64, 64, 7, 4),
+    (20000, 16, 256, 10, 2),
+    (300, 64, 256, 0, 0),
+    (129, 64, 64, 0, 0),
+]
+
+
+@pytest.mark.parametrize("m,n,h,chains,arity", SHAPES)
+def test_shapes_f64(m, n, h, chains, arity):
+    _note("case: shape m=%d n=%d h=%d chains=%d arity=%d" % (m, n, h, chains, arity))
+    A = workloads.gaussian(m, n, 1000 + m + n)
+    B = workloads.gaussian(m, 17, 2000 + m)
+    out = _run(A, B, block_rows=h, chains=chains, arity=arity)
+    g = _normalised(out["R"], out["Q"], out["QtB"])
+    _check(A, B, g, _oracle(A, B))
+    np.testing.assert_allclose(out["B_back"].cpu().numpy(), B, atol=1e-12)
+
+
+def test_zero_column_and_zero_block():
+    _note("case: zero column / zero block")
+    A = workloads.gaussian(3000, 16, 77)
+    A[:, 5] = 0.0
+    A[700:1500, :] = 0.0
+    out = _run(A, None, block_rows=128)
+    R = out["R"].cpu().numpy()
+    Q = out["Q"].cpu().numpy()
+    assert abs(R[5, 5]) == 0.0
+    assert oracle.residual(A, Q, R) <= 1e-13
+    assert oracle.orthogonality(Q) <= 1e-13
+
+
+def test_triangular_input_zero_tails():
+    _note("case: triangle over zeros")
+    rng = np.random.default_rng(5)
+    R0 = np.triu(rng.standard_normal((16, 16)))
+    A = np.vstack([R0, np.zeros((1000, 16))])
+    out = _run(A, None, block_rows=64)
+    g = _normalised(out["R"], out["Q"])
+    d = oracle.signs(R0)
+    np.testing.assert_allclose(g["R"], R0 * d[:, None], atol=1e-14)
+
+
+def test_hand_worked_combine_node():
+    """The 4x2 tree node of tests/golden/combine_4x2.json, embedded as two
+    64-row chains whose leaves are the given triangles over zeros."""
+    import json
+    import os
+    from fractions import Fraction
+    _note("case: golden combine node")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "combine_4x2.json")))
+    f = lambda rows: np.array([[float(Fraction(v)) for v in r] for r in rows])
+    A = np.zeros((128, 2))
+    A[0:2] = f(g["R0"])
+    A[64:66] = f(g["R1"])
+    out = _run(A, None, block_rows=64, chains=2)
+    np.testing.assert_allclose(out["R"].cpu().numpy(), f(g["R_raw"]), atol=1e-14)
+
+
+def test_determinism_bitwise():
+    _note("case: determinism")
+    A = workloads.gaussian(50000, 64, 3)
+    Rs = []
+    for _ in range(3):
+        out = _run(A, None)
+        Rs.append(out["R"].cpu().numpy())
+    assert np.array_equal(Rs[0], Rs[1]) and np.array_equal(Rs[0], Rs[2])
+
+
+def test_tree_shape_invariance():
+    """Sec. 2.1: any reduction tree gives the same R up to roundoff and signs."""
+    _note("case: tree shapes")
+    A = workloads.gaussian(40000, 32, 8)
+    Rs = []
+    for kw in [dict(block_rows=256), dict(block_rows=64, chains=1), dict(block_rows=128, chains=9, arity=3),
+               dict(block_rows=64, chains=625, arity=2)]:
+        out = _run(A, None, **kw)
+        Rs.append(_normalised(out["R"], out["Q"])["R"])
+    for R in Rs[1:]:
+        assert oracle.rel_err(R, Rs[0]) <= 1e-13
+
+
+def test_f32_gaussian():
+    _note("case: f32")
+    A = workloads.gaussian(30000, 32, 12).astype(np.float32)
+    B = workloads.gaussian(30000, 4, 13).astype(np.float32)
+    out = _run(A, B, dtype=torch.float32)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    g = _normalised(out["R"], out["Q"], out["QtB"])
+    o = _oracle(A64, B64)
+    assert oracle.rel_err(g["R"], o["R"]) <= 5e-4
+    assert oracle.residual(A64, g["Q"], g["R"]) <= 1e-5
+    assert oracle.orthogonality(g["Q"]) <= 1e-4
+    assert oracle.rel_err(g["thin"], o["thin"]) <= 5e-4
+
+
+def test_ill_conditioned_1e8():
+    _note("case: cond 1e8 (2^16 x 64)")
+    A = workloads.conditioned(1 << 16, 64, 1e8, 2, 3)
+    B = workloads.gaussian(1 << 16, 32, 4)
+    out = _run(A, B)
+    g = _normalised(out["R"], out["Q"], out["QtB"])
+    o = _oracle(A, B)
+    tol_q = 100 * 1e8 * U64
+    _check(A, B, g, o, rtol_r=1e-11, rtol_q=tol_q)
+
+
+def test_config2_full_size_sampled():
+    """2^20 x 64, cond 1e8: the configuration the bench times.  Sampled
+    against the oracle (plus the full R): R's leading 16 x 16 block equals the R of A[:, :16];
+    R's first 16 rows equal Q_16^T A; every column norm of R equals that of A;
+    residual and orthogonality of the full factorisation."""
+    _note("case: config2 full size")
+    A, B = workloads.cfg2()
+    Ro_full = oracle.r_of(oracle.geqrf(A)[0])
+    import paper_0808_2664_amd as tq
+    Ad = _dev(A)
+    R, qt = tq.factor(Ad)
+    Q = qt.form_q()
+    Bd = _dev(B)
+    qt.apply_qt(Bd)
+    torch.cuda.synchronize()
+    Rn = R.cpu().numpy()
+    d = oracle.signs(Rn)
+    Rn = Rn * d[:, None]
+    k = 16
+    YRk, tauk = oracle.geqrf(A[:, :k])
+    Rk = oracle.r_of(YRk)
+    dk = oracle.signs(Rk)
+    assert oracle.rel_err(Rn[:k, :k], Rk * dk[:, None]) <= 1e-11
+    top = oracle.apply_qt(YRk, tauk, A[:, k:])[:k] * dk[:, None]
+    assert oracle.rel_err(Rn[:k, k:], top) <= 1e-11
+    np.testing.assert_allclose(np.linalg.norm(Rn, axis=0), np.linalg.norm(A, axis=0), rtol=1e-12)
+    # the whole R against the oracle (about 8 s of CPU)
+    assert oracle.rel_err(Rn, Ro_full * oracle.signs(Ro_full)[:, None]) <= 1e-11
+    Qd = Q * _dev(d)[None, :]
+    Rd = _dev(Rn)
+    res = (torch.linalg.norm(_dev(A) - Qd @ Rd) / torch.linalg.norm(_dev(A))).item()
+    orth = torch.linalg.norm(_gram_pairwise(Qd) - torch.eye(64, dtype=torch.float64, device="cuda")).item()
+    assert res <= 1e-13 and orth <= 1e-13
+    # thin Q^T B: rows 0..n-1 equal Q^T B with the explicit Q
+    thin = (Bd[:64] * _dev(d)[:, None])
+    ref = Qd.T @ _dev(B)
+    assert (torch.linalg.norm(thin - ref) / torch.linalg.norm(ref)).item() <= 1e-12
