@@ -114,11 +114,35 @@ int tsqr_qtree_info(tsqr_qtree q, int64_t* info);
  * padded width.  Errors: 1 m, 2 n, 3 opts, 4 out. */
 int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out);
 
+/* CAQR (Sec. 3): right-looking QR of a general m x n matrix (m >= n) whose
+ * panel factorisation is TSQR; after panel k the panel's implicit Q^T is
+ * applied to the trailing columns, first block by block (the leaf level),
+ * then on the tree's n-row slabs (Sec. 3.1).
+ *   dtype: storage type of A; update_dtype: arithmetic of the trailing
+ *   updates (TSQR_F32 with FP64 storage = the mixed-precision update: the
+ *   two products of each block reflector run on FP32 MFMA with FP32
+ *   accumulation and are subtracted in FP64; the panel reflectors, their T
+ *   factors and the tree combines stay in the storage type).
+ *   A: device m x n (lda >= n), overwritten: R in the upper triangle of the
+ *   first n rows, the panels' reflectors below (the implicit Q borrows A).
+ *   panel: panel width b, 1..64 (0 = 64).  opts: tree shape of each panel.
+ *   q_out: receives the implicit Q (apply it with tsqr_apply_q/_qt, form it
+ *   with tsqr_form_q), or NULL.
+ *   Errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 panel, 7 update_dtype, 8 opts. */
+int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int update_dtype,
+                const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
 /* D = sign(diag R) with sign(0) = +1; R <- D R and Q <- Q D, so diag(R) >= 0
  * (the QR factorisation is unique up to these signs, Sec. 2.1).
  * Q: device m x n (ldq >= n) or NULL; R: device n x n (ldr >= n). */
 int tsqr_sign_normalize(int dtype, int64_t m, int64_t n, void* Q, int64_t ldq, void* R, int64_t ldr,
                         void* stream);
+
+/* R out of a factored matrix: dst (n x n) <- upper triangle of src (n x n
+ * view, leading dimension lds), zeros below the diagonal.  Used to read R
+ * from the first n rows of a CAQR-factored A.  Errors: 1 dtype, 2 n, 3 src,
+ * 4 lds, 5 dst, 6 ldd. */
+int tsqr_copy_r(int dtype, int64_t n, const void* src, int64_t lds, void* dst, int64_t ldd, void* stream);
 
 /* Profiling hook.  When start/stop are hipEvent_t handles (plain pointers),
  * every later call records them on its stream right before and right after

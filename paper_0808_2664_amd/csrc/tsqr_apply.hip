@@ -340,6 +340,21 @@ hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const v
     return hipErrorInvalidValue;
 }
 
+template <typename T>
+__global__ void k_fill_identity(int64_t m, int64_t n, T* __restrict__ Q, int64_t ldq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * n) return;
+    const int64_t i = e / n, j = e - i * n;
+    Q[i * ldq + j] = (i == j) ? T(1) : T(0);
+}
+
+hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t ldq, hipStream_t st) {
+    const int64_t nb = (m * n + 255) / 256;
+    if (f64) k_fill_identity<double><<<(unsigned)nb, 256, 0, st>>>(m, n, (double*)Q, ldq);
+    else k_fill_identity<float><<<(unsigned)nb, 256, 0, st>>>(m, n, (float*)Q, ldq);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st) {
     const int nb = (int)((n * n + 255) / 256);
     if (f64) k_init_formq<double><<<nb, 256, 0, st>>>(n, (double*)Q, ldq);

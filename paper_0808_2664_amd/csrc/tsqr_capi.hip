@@ -144,7 +144,7 @@ static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, vo
     }
     tsqr::work_carve(&q->wk, g, f64);
     e = tsqr::launch_factor(f64, g, A, lda, q->wk, st);
-    if (e == hipSuccess && R) e = tsqr::launch_copy_r(f64, n, q->wk.Rbuf, R, ldr, !r_upper_only, st);
+    if (e == hipSuccess && R) e = tsqr::launch_copy_r(f64, n, q->wk.Rbuf, n, R, ldr, !r_upper_only, st);
     if (e != hipSuccess) {
         (void)hipFreeAsync(q->wk.base, st);
         delete q;
@@ -229,10 +229,68 @@ int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
     if (!Q) return -2;
     if (ldq < q->n) return -3;
     hipStream_t st = (hipStream_t)stream;
-    if (q->kind != 0) return TSQR_ERR_UNSUPPORTED;
+    if (q->kind != 0) {
+        // CAQR: Q [I_n; 0] by applying the panel trees in reverse order
+        hipError_t e = tsqr::launch_fill_identity(q->f64, q->m, q->n, Q, ldq, st);
+        if (e != hipSuccess) return hip_fail(e);
+        return apply_impl(q, q->n, Q, ldq, tsqr::MODE_Q, st);
+    }
     hipError_t e = tsqr::launch_init_formq(q->f64, q->n, Q, ldq, st);
     if (e != hipSuccess) return hip_fail(e);
     return apply_one(q, q->n, Q, ldq, tsqr::MODE_FORMQ, q->f64, st);
+}
+
+int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int update_dtype,
+                const tsqr_opts* opts, tsqr_qtree* q_out, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (panel == 0) panel = 64;
+    if (panel < 1 || panel > TSQR_MAX_N) return -6;
+    if (!check_dtype(update_dtype)) return -7;
+    if (update_dtype == TSQR_F64 && dtype == TSQR_F32) return -7;
+    if (opts && opts->flags != 0) return -8;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = dtype == TSQR_F64;
+    const bool cf64 = update_dtype == TSQR_F64;
+    const size_t es = f64 ? 8 : 4;
+    tsqr_qtree_s* q = new tsqr_qtree_s();
+    q->kind = 1;
+    q->f64 = f64;
+    q->A = A;
+    q->lda = lda;
+    q->stream = st;
+    q->m = m;
+    q->n = n;
+    q->panel = panel;
+    // Right-looking QR with TSQR panels (Sec. 3): factor panel k, then apply
+    // its implicit Q^T to the trailing columns (Sec. 3.1, leaf then tree level).
+    for (int64_t r0 = 0; r0 < n; r0 += panel) {
+        const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
+        const int64_t rows = m - r0;
+        char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
+        tsqr_qtree_s* pq = nullptr;
+        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, opts, &pq, st);
+        if (rc != 0) {
+            destroy_impl(q);
+            return rc == -1 ? -2 : rc;
+        }
+        q->panels.push_back(pq);
+        const int64_t tc = n - r0 - cols;
+        if (tc > 0) {
+            hipError_t e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, P + (size_t)cols * es, lda,
+                                              tc, tsqr::MODE_QT, st);
+            if (e != hipSuccess) {
+                destroy_impl(q);
+                return hip_fail(e);
+            }
+        }
+    }
+    if (q_out) *q_out = q;
+    else destroy_impl(q);
+    return 0;
 }
 
 int tsqr_qtree_destroy(tsqr_qtree q) {
@@ -272,6 +330,18 @@ int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out
     out[5] = g.nblocks;
     out[6] = g.NC;
     return 0;
+}
+
+int tsqr_copy_r(int dtype, int64_t n, const void* src, int64_t lds, void* dst, int64_t ldd, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (n < 0) return -2;
+    if (!src) return -3;
+    if (lds < n) return -4;
+    if (!dst) return -5;
+    if (ldd < n) return -6;
+    if (n == 0) return 0;
+    hipError_t e = tsqr::launch_copy_r(dtype == TSQR_F64, n, src, lds, dst, ldd, true, (hipStream_t)stream);
+    return e == hipSuccess ? 0 : hip_fail(e);
 }
 
 int tsqr_last_hip_error(void) { return g_last_hip; }

@@ -78,11 +78,12 @@ inline void phase_end(int p, hipStream_t st) {
 
 // Launchers (defined in the .hip files).  Return a hipError_t.
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, hipStream_t st);
-hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, void* R, int64_t ldr, bool zero_lower,
+hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, int64_t lds, void* R, int64_t ldr, bool zero_lower,
                          hipStream_t st);
 hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const void* Y, int64_t ldy,
                         const Work& wk, void* B, int64_t ldb, int64_t k, int mode, hipStream_t st);
 hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t ldq, hipStream_t st);
 
 }  // namespace tsqr
 

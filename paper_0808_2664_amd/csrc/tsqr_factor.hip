@@ -549,11 +549,12 @@ __global__ __launch_bounds__(64 * CombineShape<NC>::NW) void k_tree_combine(Geom
 }
 
 template <typename T>
-__global__ void k_copy_r(int64_t n, const T* __restrict__ Rsrc, T* __restrict__ R, int64_t ldr, int zero_lower) {
+__global__ void k_copy_r(int64_t n, const T* __restrict__ Rsrc, int64_t lds, T* __restrict__ R, int64_t ldr,
+                         int zero_lower) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     const int64_t i = e / n, j = e - i * n;
-    if (j >= i) R[i * ldr + j] = Rsrc[e];
+    if (j >= i) R[i * ldr + j] = Rsrc[i * lds + j];
     else if (zero_lower) R[i * ldr + j] = T(0);
 }
 
@@ -600,14 +601,14 @@ hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Wo
     return f64 ? factor_t<double>(g, (double*)A, lda, wk, st) : factor_t<float>(g, (float*)A, lda, wk, st);
 }
 
-hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, void* R, int64_t ldr, bool zero_lower,
+hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, int64_t lds, void* R, int64_t ldr, bool zero_lower,
                          hipStream_t st) {
     const int64_t tot = n * n;
-    const int nb = (int)((tot + 255) / 256);
+    const int64_t nb = (tot + 255) / 256;
     if (f64)
-        k_copy_r<double><<<nb, 256, 0, st>>>(n, (const double*)Rsrc, (double*)R, ldr, zero_lower ? 1 : 0);
+        k_copy_r<double><<<(unsigned)nb, 256, 0, st>>>(n, (const double*)Rsrc, lds, (double*)R, ldr, zero_lower ? 1 : 0);
     else
-        k_copy_r<float><<<nb, 256, 0, st>>>(n, (const float*)Rsrc, (float*)R, ldr, zero_lower ? 1 : 0);
+        k_copy_r<float><<<(unsigned)nb, 256, 0, st>>>(n, (const float*)Rsrc, lds, (float*)R, ldr, zero_lower ? 1 : 0);
     return hipGetLastError();
 }
 

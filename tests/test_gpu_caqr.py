@@ -1,0 +1,111 @@
+"""GPU parity of CAQR (TSQR panels + trailing update, Sec. 3) against the oracle.
+
+FP64 updates: normwise R error <= 1e-11 and backward error ||A - QR||/||A||
+<= 1e-13.  FP32 updates on FP64 storage: the error is stated per result;
+the gates here are the FP32 scale (1e-4), far above what a correct run gives
+(~1e-6) and far below what a wrong reflector or sign gives (~1).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype=dtype)
+
+
+def _backward_error(qt, A_dev, R, m, n):
+    X = torch.zeros(m, n, dtype=A_dev.dtype, device="cuda")
+    X[:n] = R
+    qt.apply_q(X)
+    return (torch.linalg.norm((X - A_dev).double()) / torch.linalg.norm(A_dev.double())).item()
+
+
+def _run(A, panel=64, update=None, dtype=torch.float64, **kw):
+    import paper_0808_2664_amd as tq
+    Ad = _dev(A, dtype)
+    A_keep = Ad.clone()
+    R, qt = tq.caqr(Ad, panel=panel, update=update, **kw)
+    torch.cuda.synchronize()
+    return R, qt, A_keep
+
+
+@pytest.mark.parametrize("m,n,panel", [(768, 768, 64), (3000, 700, 64), (1000, 1000, 32), (513, 200, 16),
+                                       (2049, 130, 64)])
+def test_caqr_f64(m, n, panel):
+    _note("case: caqr f64 m=%d n=%d panel=%d" % (m, n, panel))
+    A = workloads.gaussian(m, n, 300 + m + n)
+    R, qt, A_keep = _run(A, panel=panel)
+    info = qt.info()
+    assert info["kind"] == 1 and info["panel"] == panel
+    Rg = R.cpu().numpy()
+    d = oracle.signs(Rg)
+    Qo, Ro = oracle.qr(A)
+    assert oracle.rel_err(Rg * d[:, None], Ro) <= 1e-11
+    be = _backward_error(qt, A_keep, R, m, n)
+    assert be <= 1e-13, be
+    Q = qt.form_q().cpu().numpy()
+    assert oracle.orthogonality(Q) <= 1e-13
+    assert oracle.residual(A, Q, Rg) <= 1e-13
+
+
+def test_caqr_f32_update_on_f64_storage():
+    _note("case: caqr fp32 update 1024^2")
+    A = workloads.gaussian(1024, 1024, 77)
+    R64, _, _ = _run(A, update=torch.float64)
+    R32, qt, A_keep = _run(A, update=torch.float32)
+    Qo, Ro = oracle.qr(A)
+    e64 = oracle.rel_err(R64.cpu().numpy() * oracle.signs(R64.cpu().numpy())[:, None], Ro)
+    e32 = oracle.rel_err(R32.cpu().numpy() * oracle.signs(R32.cpu().numpy())[:, None], Ro)
+    be32 = _backward_error(qt, A_keep, R32, 1024, 1024)
+    _note("  R error fp64-update %.2e, fp32-update %.2e; backward error fp32-update %.2e" % (e64, e32, be32))
+    assert e64 <= 1e-11
+    assert 1e-12 < e32 <= 1e-4      # the FP32 products really ran (error above FP64 level)
+    assert be32 <= 1e-4
+
+
+def test_caqr_f32_storage():
+    _note("case: caqr f32 storage")
+    A = workloads.gaussian(1200, 500, 91).astype(np.float32)
+    R, qt, A_keep = _run(A, dtype=torch.float32)
+    Ro = oracle.qr(A.astype(np.float64))[1]
+    Rg = R.double().cpu().numpy()
+    assert oracle.rel_err(Rg * oracle.signs(Rg)[:, None], Ro) <= 5e-4
+    assert _backward_error(qt, A_keep, R, 1200, 500) <= 1e-5
+
+
+def test_caqr_config3_full_size_sampled():
+    """16384 x 16384 Gaussian (seed 5), panel 64: sampled against the oracle.
+    R[:k,:k] is the R of A[:, :k]; R[:k, j] = Q_k^T a_j for sampled j; the
+    column norms of R equal those of A; backward error on the GPU."""
+    _note("case: caqr 16384^2 f64 (sampled)")
+    N = 16384
+    A = workloads.cfg3(N)
+    R, qt, A_keep = _run(A)
+    Rg = R.cpu().numpy()
+    d = oracle.signs(Rg)
+    Rn = Rg * d[:, None]
+    k = 64
+    YRk, tauk = oracle.geqrf(A[:, :k])
+    Rk = oracle.r_of(YRk)
+    dk = oracle.signs(Rk)
+    assert oracle.rel_err(Rn[:k, :k], Rk * dk[:, None]) <= 1e-11
+    cols = np.array([100, 5000, 9999, 16383])
+    top = oracle.apply_qt(YRk, tauk, A[:, cols])[:k] * dk[:, None]
+    assert oracle.rel_err(Rn[:k, cols], top) <= 1e-11
+    np.testing.assert_allclose(np.linalg.norm(Rn, axis=0), np.linalg.norm(A, axis=0), rtol=1e-11)
+    be = _backward_error(qt, A_keep, R, N, N)
+    _note("  backward error %.2e" % be)
+    assert be <= 1e-13
