@@ -138,6 +138,24 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
 int tsqr_sign_normalize(int dtype, int64_t m, int64_t n, void* Q, int64_t ldq, void* R, int64_t ldr,
                         void* stream);
 
+/* Adjoint of the thin QR with diag(R) > 0 (the sign-normalised factors of
+ * tsqr_sign_normalize), for reverse-mode differentiation.  Not in the paper:
+ * the published QR adjoint (Walter & Lehmann; Liao et al. "copyltu" form)
+ *     M = R triu(dR)^T - dQ^T Q,  C = tril(M) + tril(M,-1)^T,
+ *     dA = (dQ + Q C) R^{-T}.
+ * The m-long contraction dQ^T Q is reduced over row chunks like the TSQR tree;
+ * dA is one streaming pass over dQ and Q.  No reflectors are needed.
+ *   batch >= 1 matrices, each m x n (n <= 64), matrix b at pointer + b*stride.
+ *   Q, R: forward outputs (R upper, positive diagonal).  dQ, dR: upstream
+ *   gradients, either may be NULL (= zero); only triu(dR) is used.
+ *   dA: output m x n.  All device pointers, row-major.
+ *   Errors: 1 dtype, 2 batch, 3 m, 4 n, 5 Q, 6 ldq, 8 R, 9 ldr, 12 lddq,
+ *   15 lddr, 17 dA, 18 ldda. */
+int tsqr_backward(int dtype, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t strideQ,
+                  const void* R, int64_t ldr, int64_t strideR, const void* dQ, int64_t lddq, int64_t stridedQ,
+                  const void* dR, int64_t lddr, int64_t stridedR, void* dA, int64_t ldda, int64_t stridedA,
+                  void* stream);
+
 /* R out of a factored matrix: dst (n x n) <- upper triangle of src (n x n
  * view, leading dimension lds), zeros below the diagonal.  Used to read R
  * from the first n rows of a CAQR-factored A.  Errors: 1 dtype, 2 n, 3 src,

@@ -1,0 +1,266 @@
+// Reverse-mode derivative (adjoint) of the thin QR map A -> (Q, R) with
+// diag(R) > 0, for the differentiable TSQR.  Not in the paper: the published
+// QR adjoint (Walter & Lehmann; Liao, Liu, Wang & Xiang, "copyltu" form):
+//     M  = R triu(dR)^T - dQ^T Q,   C = tril(M) + tril(M, -1)^T,
+//     dA = (dQ + Q C) R^{-T} = dQ Y + Q X,   Y = R^{-T},  X = C R^{-T}.
+// The m-long contraction dQ^T Q is reduced like the TSQR tree: row chunks,
+// each a sum of MFMA products, then the chunk partials in a fixed order.
+// The n x n work (M, C, R^{-1}) runs in one workgroup per matrix; R^{-1} uses
+// the same block recurrence as the T factors (inverse of an upper triangle:
+// T12 = -T11 U12 T22).  dA is one streaming pass over dQ and Q on MFMA.
+#include "tsqr_common.hpp"
+
+namespace tsqr {
+using namespace dev;
+
+// Partial Gram dQ^T Q over rows [ch*CR, (ch+1)*CR) of matrix b.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restrict__ dQ, int64_t lddq, int64_t sdq,
+                                              const T* __restrict__ Q, int64_t ldq, int64_t sq, int64_t CR,
+                                              T* __restrict__ part) {
+    typedef Mfma<T> M;
+    typedef typename M::acc acc_t;
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    constexpr int NP = NCP / 16;
+    __shared__ T red[4][16][17];
+    const int b = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const T* dq = dQ + (int64_t)b * sdq;
+    const T* q = Q + (int64_t)b * sq;
+    const int64_t lo = (int64_t)ch * CR, hi = (lo + CR < m) ? lo + CR : m;
+    acc_t acc[NP][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) acc[p][c] = acc_t{0, 0, 0, 0};
+    for (int64_t r0 = lo + 16 * wv; r0 < hi; r0 += 64) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + M::orow(l4, i);
+            T a[NP], bq[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int cc = 16 * p + l16;
+                const bool ok = (r < hi) && (cc < n);
+                a[p] = ok ? dq[r * lddq + cc] : T(0);
+                bq[p] = ok ? q[r * ldq + cc] : T(0);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int c = 0; c < NP; ++c) acc[p][c] = M::mma(a[p], bq[c], acc[p][c]);
+        }
+    }
+    T* out = part + ((int64_t)b * nch + ch) * NCP * NCP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wv][M::orow(l4, r)][l16] = acc[p][c][r];
+            __syncthreads();
+            {
+                const int i = tid >> 4, j = tid & 15;
+                T s = red[0][i][j] + red[1][i][j];
+                s += red[2][i][j];
+                s += red[3][i][j];
+                out[(16 * p + i) * NCP + 16 * c + j] = s;
+            }
+            __syncthreads();
+        }
+}
+
+// G[b] = sum over chunks (fixed order) of the partials.
+template <typename T, int NC>
+__global__ void k_gram_reduce(int nch, const T* __restrict__ part, T* __restrict__ G) {
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    const int b = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NCP * NCP) return;
+    const T* p = part + (int64_t)b * nch * NCP * NCP + e;
+    T s = T(0);
+    for (int c = 0; c < nch; ++c) s += p[(int64_t)c * NCP * NCP];
+    G[(int64_t)b * NCP * NCP + e] = s;
+}
+
+// Per matrix: X = copyltu(R triu(dR)^T - G) R^{-T} and Y = R^{-T}.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_adjoint_small(int n, const T* __restrict__ R, int64_t ldr, int64_t sr,
+                                                       const T* __restrict__ dR, int64_t lddr, int64_t sdr,
+                                                       const T* __restrict__ G, int has_dq, T* __restrict__ XY) {
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    __shared__ T Rs[NCP][NCP + 1];
+    __shared__ T Ui[NCP][NCP + 1];  // R^{-1}, built in place
+    __shared__ T Cm[NCP][NCP + 1];
+    __shared__ T tmp[(NCP / 2) * (NCP / 2)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const T* r = R + (int64_t)b * sr;
+    const T* dr = dR ? dR + (int64_t)b * sdr : nullptr;
+    const T* g = G + (int64_t)b * NCP * NCP;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        const T v = (i < n && j < n && j >= i) ? r[i * ldr + j] : T(0);
+        Rs[i][j] = v;
+        Ui[i][j] = (i == j) ? ((i < n) ? T(1) / v : T(0)) : v;
+    }
+    __syncthreads();
+    // M = R triu(dR)^T - G  (Cm holds M)
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        T a = T(0);
+        if (i < n && j < n) {
+            if (dr) {
+                const int k0 = i > j ? i : j;
+                for (int k = k0; k < n; ++k) a = fma(Rs[i][k], dr[j * lddr + k], a);
+            }
+            if (has_dq) a -= g[i * NCP + j];
+        }
+        Cm[i][j] = a;
+    }
+    // R^{-1} by the block recurrence on diagonal blocks of size 1, 2, 4, ...
+    for (int s = 1; s < NCP; s *= 2) {
+        const int npairs = NCP / (2 * s), ss = s * s;
+        __syncthreads();
+        for (int e = tid; e < npairs * ss; e += 256) {
+            const int pr = e / ss, rem = e - pr * ss, i = rem / s, jj = rem - i * s;
+            const int o = 2 * s * pr;
+            T a = T(0);
+            for (int l = 0; l <= jj; ++l) a = fma(Ui[o + i][o + s + l], Ui[o + s + l][o + s + jj], a);
+            tmp[e] = a;
+        }
+        __syncthreads();
+        for (int e = tid; e < npairs * ss; e += 256) {
+            const int pr = e / ss, rem = e - pr * ss, i = rem / s, jj = rem - i * s;
+            const int o = 2 * s * pr;
+            T a = T(0);
+            for (int l = i; l < s; ++l) a = fma(Ui[o + i][o + l], tmp[pr * ss + l * s + jj], a);
+            Ui[o + i][o + s + jj] = -a;
+        }
+    }
+    __syncthreads();
+    // X = C R^{-T}, C = copyltu(M);  Y = R^{-T}
+    T* X = XY + (int64_t)b * 2 * NCP * NCP;
+    T* Y = X + NCP * NCP;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        T a = T(0);
+        if (i < n && j < n) {
+            for (int k = j; k < n; ++k) {
+                const T c = (i >= k) ? Cm[i][k] : Cm[k][i];
+                a = fma(c, Ui[j][k], a);
+            }
+        }
+        X[i * NCP + j] = a;
+        Y[i * NCP + j] = (i < n && j < n && i >= j) ? Ui[j][i] : T(0);
+    }
+}
+
+// dA = dQ Y + Q X over 256-row blocks (4 waves x 64 rows).
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_adjoint_stream(int64_t m, int n, const T* __restrict__ dQ, int64_t lddq,
+                                                        int64_t sdq, const T* __restrict__ Q, int64_t ldq,
+                                                        int64_t sq, const T* __restrict__ XY, T* __restrict__ dA,
+                                                        int64_t ldda, int64_t sda) {
+    typedef Mfma<T> M;
+    typedef typename M::acc acc_t;
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    constexpr int NP = NCP / 16;
+    constexpr int NK = NCP / 4;
+    __shared__ T Xs[NCP][NCP + 1];
+    __shared__ T Ys[NCP][NCP + 1];
+    const int b = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const T* xy = XY + (int64_t)b * 2 * NCP * NCP;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        Xs[i][j] = xy[e];
+        Ys[i][j] = xy[NCP * NCP + e];
+    }
+    __syncthreads();
+    const T* dq = dQ ? dQ + (int64_t)b * sdq : nullptr;
+    const T* q = Q + (int64_t)b * sq;
+    T* da = dA + (int64_t)b * sda;
+    const int64_t base = (int64_t)blockIdx.x * 256 + 64 * wv;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int64_t rr = base + 16 * s + l16;  // A-operand row of this lane
+        T adq[NK], aq[NK];
+#pragma unroll
+        for (int k4 = 0; k4 < NK; ++k4) {
+            const int cc = 4 * k4 + l4;
+            const bool ok = (rr < m) && (cc < n);
+            adq[k4] = (ok && dq) ? dq[rr * lddq + cc] : T(0);
+            aq[k4] = ok ? q[rr * ldq + cc] : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            acc_t u = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int k4 = 0; k4 < NK; ++k4) {
+                u = M::mma(adq[k4], Ys[4 * k4 + l4][16 * c + l16], u);
+                u = M::mma(aq[k4], Xs[4 * k4 + l4][16 * c + l16], u);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = base + 16 * s + M::orow(l4, r);
+                const int col = 16 * c + l16;
+                if (row < m && col < n) da[row * ldda + col] = u[r];
+            }
+        }
+    }
+}
+
+template <typename T, int NC>
+static hipError_t backward_nc(int64_t batch, int64_t m, int n, const T* Q, int64_t ldq, int64_t sq, const T* R,
+                              int64_t ldr, int64_t sr, const T* dQ, int64_t lddq, int64_t sdq, const T* dR,
+                              int64_t lddr, int64_t sdr, T* dA, int64_t ldda, int64_t sda, hipStream_t st) {
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    // chunks of whole 64-row steps, ~2048 workgroups in total
+    int64_t CR = (m * batch + 2047) / 2048;
+    CR = ((CR + 255) / 256) * 256;
+    if (CR < 256) CR = 256;
+    const int64_t nch = (m + CR - 1) / CR;
+    const size_t es = sizeof(T);
+    const size_t bytes = (size_t)batch * (nch + 1 + 2) * NCP * NCP * es;
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, bytes, st);
+    if (e != hipSuccess) return e;
+    T* part = (T*)ws;
+    T* G = part + (size_t)batch * nch * NCP * NCP;
+    T* XY = G + (size_t)batch * NCP * NCP;
+    if (dQ) {
+        k_gram<T, NC><<<dim3((unsigned)nch, (unsigned)batch), 256, 0, st>>>(m, n, dQ, lddq, sdq, Q, ldq, sq, CR, part);
+        k_gram_reduce<T, NC><<<dim3((NCP * NCP + 255) / 256, (unsigned)batch), 256, 0, st>>>((int)nch, part, G);
+    }
+    k_adjoint_small<T, NC><<<(unsigned)batch, 256, 0, st>>>(n, R, ldr, sr, dR, lddr, sdr, G, dQ ? 1 : 0, XY);
+    k_adjoint_stream<T, NC><<<dim3((unsigned)((m + 255) / 256), (unsigned)batch), 256, 0, st>>>(
+        m, n, dQ, lddq, sdq, Q, ldq, sq, XY, dA, ldda, sda);
+    e = hipGetLastError();
+    hipError_t e2 = hipFreeAsync(ws, st);
+    return e != hipSuccess ? e : e2;
+}
+
+template <typename T>
+static hipError_t backward_t(int64_t batch, int64_t m, int n, const T* Q, int64_t ldq, int64_t sq, const T* R,
+                             int64_t ldr, int64_t sr, const T* dQ, int64_t lddq, int64_t sdq, const T* dR, int64_t lddr,
+                             int64_t sdr, T* dA, int64_t ldda, int64_t sda, hipStream_t st) {
+    if (n <= 16)
+        return backward_nc<T, 16>(batch, m, n, Q, ldq, sq, R, ldr, sr, dQ, lddq, sdq, dR, lddr, sdr, dA, ldda, sda, st);
+    if (n <= 32)
+        return backward_nc<T, 32>(batch, m, n, Q, ldq, sq, R, ldr, sr, dQ, lddq, sdq, dR, lddr, sdr, dA, ldda, sda, st);
+    return backward_nc<T, 64>(batch, m, n, Q, ldq, sq, R, ldr, sr, dQ, lddq, sdq, dR, lddr, sdr, dA, ldda, sda, st);
+}
+
+hipError_t launch_backward(bool f64, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t sq,
+                           const void* R, int64_t ldr, int64_t sr, const void* dQ, int64_t lddq, int64_t sdq,
+                           const void* dR, int64_t lddr, int64_t sdr, void* dA, int64_t ldda, int64_t sda,
+                           hipStream_t st) {
+    if (f64)
+        return backward_t<double>(batch, m, (int)n, (const double*)Q, ldq, sq, (const double*)R, ldr, sr,
+                                  (const double*)dQ, lddq, sdq, (const double*)dR, lddr, sdr, (double*)dA, ldda, sda,
+                                  st);
+    return backward_t<float>(batch, m, (int)n, (const float*)Q, ldq, sq, (const float*)R, ldr, sr, (const float*)dQ,
+                             lddq, sdq, (const float*)dR, lddr, sdr, (float*)dA, ldda, sda, st);
+}
+
+}  // namespace tsqr

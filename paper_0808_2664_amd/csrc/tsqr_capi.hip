@@ -344,6 +344,29 @@ int tsqr_copy_r(int dtype, int64_t n, const void* src, int64_t lds, void* dst, i
     return e == hipSuccess ? 0 : hip_fail(e);
 }
 
+int tsqr_backward(int dtype, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t strideQ,
+                  const void* R, int64_t ldr, int64_t strideR, const void* dQ, int64_t lddq, int64_t stridedQ,
+                  const void* dR, int64_t lddr, int64_t stridedR, void* dA, int64_t ldda, int64_t stridedA,
+                  void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (batch < 1) return -2;
+    if (m < 1) return -3;
+    if (n < 1 || n > m) return n > m ? -3 : -4;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!Q) return -5;
+    if (ldq < n) return -6;
+    if (!R) return -8;
+    if (ldr < n) return -9;
+    if (dQ && lddq < n) return -12;
+    if (dR && lddr < n) return -15;
+    if (!dA) return -17;
+    if (ldda < n) return -18;
+    if (batch > 65535) return -2;
+    hipError_t e = tsqr::launch_backward(dtype == TSQR_F64, batch, m, n, Q, ldq, strideQ, R, ldr, strideR, dQ, lddq,
+                                         stridedQ, dR, lddr, stridedR, dA, ldda, stridedA, (hipStream_t)stream);
+    return e == hipSuccess ? 0 : hip_fail(e);
+}
+
 int tsqr_last_hip_error(void) { return g_last_hip; }
 
 int tsqr_set_phase_events(int phase, void* start, void* stop) {

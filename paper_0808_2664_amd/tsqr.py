@@ -165,3 +165,55 @@ def qr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
     sign_normalize(Q, R)
     qt.close()
     return Q, R
+
+
+def qr_backward(Q: torch.Tensor, R: torch.Tensor, dQ: torch.Tensor | None, dR: torch.Tensor | None) -> torch.Tensor:
+    """dA for the sign-normalised thin QR (2-D, or batched 3-D tensors)."""
+    lib = _lib.load()
+    batched = Q.dim() == 3
+    Qb = Q if batched else Q.unsqueeze(0)
+    Rb = R if batched else R.unsqueeze(0)
+    B, m, n = Qb.shape
+    dQb = None if dQ is None else (dQ if batched else dQ.unsqueeze(0)).contiguous()
+    dRb = None if dR is None else (dR if batched else dR.unsqueeze(0)).contiguous()
+    Qb = Qb.contiguous()
+    Rb = Rb.contiguous()
+    dA = torch.empty_like(Qb)
+    rc = lib.tsqr_backward(_dtype_code(Qb), B, m, n, _ptr(Qb), n, m * n, _ptr(Rb), n, n * n,
+                           _ptr(dQb) if dQb is not None else None, n, m * n,
+                           _ptr(dRb) if dRb is not None else None, n, n * n,
+                           _ptr(dA), n, m * n, _stream(Qb))
+    _lib.check("tsqr_backward", rc)
+    return dA if batched else dA[0]
+
+
+class TSQRFunction(torch.autograd.Function):
+    """A -> (Q, R), thin QR with diag(R) >= 0 by TSQR; backward by the QR
+    adjoint kernels (no stored reflectors).  A may be 2-D or a 3-D batch."""
+
+    @staticmethod
+    def forward(ctx, A, block_rows=0, chains=0, arity=0):
+        batched = A.dim() == 3
+        As = A.detach().contiguous()
+        if batched:
+            Qs, Rs = [], []
+            for b in range(As.shape[0]):
+                Qb, Rb = qr(As[b], block_rows=block_rows, chains=chains, arity=arity)
+                Qs.append(Qb)
+                Rs.append(Rb)
+            Q, R = torch.stack(Qs), torch.stack(Rs)
+        else:
+            Q, R = qr(As, block_rows=block_rows, chains=chains, arity=arity)
+        ctx.save_for_backward(Q, R)
+        return Q, R
+
+    @staticmethod
+    def backward(ctx, dQ, dR):
+        Q, R = ctx.saved_tensors
+        dA = qr_backward(Q, R, dQ, dR)
+        return dA, None, None, None
+
+
+def tsqr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
+    """Differentiable thin QR (Q, R) with diag(R) >= 0."""
+    return TSQRFunction.apply(A, block_rows, chains, arity)
