@@ -45,20 +45,25 @@ namespace tsqr {
 
 int padded_nc(int64_t n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64; }
 
+// Chains by default: one one-wave chain per SIMD (4 per CU on 256 CUs), the
+// number the factor kernel keeps resident at once.
+constexpr int64_t kDefaultChains = 1024;
+
 // Tree geometry for (m, n): chains of whole blocks, the last chain absorbing
 // a remainder too short to hold an n x n leaf (a chain's first block must hold
 // n rows: its R is an n x n triangle).
 int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     if (n < 1 || n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     if (m < n) return -1;
-    int h = (o && o->block_rows) ? o->block_rows : env_int("TSQR_BLOCK_ROWS", 256);
+    const int NC = padded_nc(n);
+    int h = (o && o->block_rows) ? o->block_rows : env_int("TSQR_BLOCK_ROWS", wave_default_h(NC));
     int chains = (o && o->chains) ? o->chains : env_int("TSQR_CHAINS", 0);
     int arity = (o && o->arity) ? o->arity : env_int("TSQR_ARITY", 2);
     if (o && o->flags != 0) return TSQR_ERR_UNSUPPORTED;
-    if (h != 64 && h != 128 && h != 256) return TSQR_ERR_UNSUPPORTED;
+    if (!wave_shape_ok(NC, h)) return TSQR_ERR_UNSUPPORTED;
     if (arity < 2 || chains < 0) return TSQR_ERR_UNSUPPORTED;
     const int64_t blocks_total = (m + h - 1) / h;
-    int64_t W0 = chains > 0 ? chains : (blocks_total < 512 ? blocks_total : 512);
+    int64_t W0 = chains > 0 ? chains : (blocks_total < kDefaultChains ? blocks_total : kDefaultChains);
     if (W0 < 1) W0 = 1;
     if (W0 > blocks_total) W0 = blocks_total;
     int64_t per = (m + W0 - 1) / W0;               // rows per chain before rounding
@@ -89,8 +94,9 @@ size_t work_bytes(const Geom& g, bool f64) {
     const size_t es = f64 ? 8 : 4;
     const size_t n = (size_t)g.n, tri = n * (n + 1) / 2;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + 3 * al((size_t)g.W * n * n * es) +
-           al((size_t)g.W * tri * es) + al((size_t)g.W * n * es);
+    const size_t ncnt = (size_t)g.W * (g.levels > 0 ? g.levels : 1);
+    return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + 2 * al((size_t)g.W * n * n * es) +
+           al((size_t)g.W * tri * es) + al((size_t)g.W * n * es) + al(ncnt * 4);
 }
 
 void work_carve(Work* w, const Geom& g, bool f64) {
@@ -110,7 +116,7 @@ void work_carve(Work* w, const Geom& g, bool f64) {
     p += al((size_t)g.W * tri * es);
     w->tau_node = p;
     p += al((size_t)g.W * n * es);
-    // third n*n*W slot: scratch (unused slot kept so layouts stay aligned)
+    w->cnt = (int*)p;
 }
 
 }  // namespace tsqr
@@ -143,8 +149,7 @@ static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, vo
         return hip_fail(e);
     }
     tsqr::work_carve(&q->wk, g, f64);
-    e = tsqr::launch_factor(f64, g, A, lda, q->wk, st);
-    if (e == hipSuccess && R) e = tsqr::launch_copy_r(f64, n, q->wk.Rbuf, n, R, ldr, !r_upper_only, st);
+    e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, !r_upper_only, st);
     if (e != hipSuccess) {
         (void)hipFreeAsync(q->wk.base, st);
         delete q;

@@ -56,6 +56,7 @@ struct Work {
     void* Ynode = nullptr;     // W x n x n  (slot c holds the step folding chain c)
     void* Tnode = nullptr;     // W x n(n+1)/2
     void* tau_node = nullptr;  // W x n
+    int* cnt = nullptr;        // W x levels node arrival counters
 };
 
 enum ApplyMode { MODE_QT = 0, MODE_Q = 1, MODE_FORMQ = 2 };
@@ -77,7 +78,13 @@ inline void phase_end(int p, hipStream_t st) {
 }
 
 // Launchers (defined in the .hip files).  Return a hipError_t.
-hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, hipStream_t st);
+// TSQR of A into the reflectors (in A), the tree of Q factors (wk) and R
+// (row-major, ldr; zeros below the diagonal when zero_lower; R may be null).
+hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
+                         bool zero_lower, hipStream_t st);
+// Block shapes of the factor kernel: rows per block h for NC padded columns.
+bool wave_shape_ok(int NC, int h);
+int wave_default_h(int NC);
 hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, int64_t lds, void* R, int64_t ldr, bool zero_lower,
                          hipStream_t st);
 hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const void* Y, int64_t ldy,
@@ -160,7 +167,10 @@ struct Mfma<double> {
     __device__ __forceinline__ static acc mma(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    __device__ __forceinline__ static int orow(int l4, int r) { return 4 * r + l4; }
+    __host__ __device__ static constexpr int orow(int l4, int r) { return 4 * r + l4; }
+    // register and 16-lane row holding output row rho (inverse of orow)
+    __host__ __device__ static constexpr int row_reg(int rho) { return rho >> 2; }
+    __host__ __device__ static constexpr int row_l4(int rho) { return rho & 3; }
 };
 template <>
 struct Mfma<float> {
@@ -168,7 +178,9 @@ struct Mfma<float> {
     __device__ __forceinline__ static acc mma(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    __device__ __forceinline__ static int orow(int l4, int r) { return 4 * l4 + r; }
+    __host__ __device__ static constexpr int orow(int l4, int r) { return 4 * l4 + r; }
+    __host__ __device__ static constexpr int row_reg(int rho) { return rho & 3; }
+    __host__ __device__ static constexpr int row_l4(int rho) { return rho >> 2; }
 };
 
 }  // namespace dev

@@ -1,0 +1,665 @@
+// One-wave Householder engine of the TSQR kernels (gfx950, wave64).
+//
+// A single wave owns one chain of row blocks (the flat tree of sequential
+// TSQR, Sec. 2.1) and, on the reduction tree, the nodes it reaches last.  No
+// workgroup barrier is ever taken: every reduction is a lane exchange inside
+// the wave, so the 8 XCDs x 32 CUs run up to 8 independent chains per CU and
+// the latency of one chain's column steps is hidden by the others.
+//
+// Register tile (the MFMA operand layout).  A block of 16*SG rows (SG = 4:
+// 64-row blocks, so a lane holds at most 64 entries of an n <= 64 tile) and
+// NCP = 16*NP columns sits in x[s][i][q]: lane l holds column 16q + l%16 of row
+// 16s + orow(l/16, i).  Column c therefore lives in the 4 lanes l%16 == c%16 of
+// one register group, and its reductions are one DPP broadcast per register
+// plus two lane swaps (v_permlane16/32_swap).
+//
+// Local QR of one block (wave_block): blocked Householder QR in panels of 16
+// columns.  Reflectors follow Sec. 5.2 (unit topmost entry): for column j,
+// beta = -sign(alpha)||x||, sign(0) = +1, tau = (beta - alpha)/beta, and
+// tau = 0 when the tail below the head is zero.  A panel is reduced column by
+// column with one lane reduction per column: g_c = sum over the tail rows of
+// x_j x_c for every column c at once gives sigma^2 = g_j and
+// v_j^T x_c = head_c + scale_j g_c.  The panel then updates the trailing
+// columns as the block reflector I - V T V^T (the compact form cited in
+// Sec. 2.1 and used by the trailing update of Sec. 3.1): W = V^T X,
+// W' = T^T W and X -= V W' are three MFMA products.  T is the forward
+// block-reflector factor, upper triangular, grown panel by panel
+// (T12 = -T11 (V1^T V2) T22): the panel's diagonal block is built during the
+// column sweep from the in-panel Gram entries, the off-diagonal blocks by MFMA
+// from the Gram blocks V_q^T V_p that the W product yields.
+//
+// Three block kinds (MODE):
+//   0  first block of a chain: the heads lie inside the tile (rows < n);
+//   1  a block stacked under the on-chip R of its chain (heads = R rows);
+//   2  a tree node: the tile is a child's upper triangular R, stacked under
+//      the node's R (Sec. 2.1, Eqs. TSQR_binarytree_2/3).  Row group s of the
+//      tile is zero in panels p < s, so panel p works on groups 0..p only and
+//      the zeros of the triangle stay exact.
+// The on-chip R (packed upper triangle) and a 16 x 17 staging tile are the
+// wave's only LDS.
+#pragma once
+#include <type_traits>
+
+#include "tsqr_common.hpp"
+
+namespace tsqr {
+using namespace dev;
+
+template <int I>
+using ic_t = std::integral_constant<int, I>;
+
+// Compile-time loop: f(ic_t<B>), ..., f(ic_t<E-1>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(ic_t<B>{});
+        sfor<B + 1, E>(static_cast<F&&>(f));
+    }
+}
+
+// ---- lane helpers -----------------------------------------------------------
+__device__ __forceinline__ double swapsum(double x, bool sixteen) {
+    struct P { int lo, hi; };
+    P p = __builtin_bit_cast(P, x);
+    if (sixteen) {
+        auto a = __builtin_amdgcn_permlane16_swap(p.lo, p.lo, false, false);
+        auto b = __builtin_amdgcn_permlane16_swap(p.hi, p.hi, false, false);
+        P d0 = {(int)a[0], (int)b[0]}, d1 = {(int)a[1], (int)b[1]};
+        return __builtin_bit_cast(double, d0) + __builtin_bit_cast(double, d1);
+    } else {
+        auto a = __builtin_amdgcn_permlane32_swap(p.lo, p.lo, false, false);
+        auto b = __builtin_amdgcn_permlane32_swap(p.hi, p.hi, false, false);
+        P d0 = {(int)a[0], (int)b[0]}, d1 = {(int)a[1], (int)b[1]};
+        return __builtin_bit_cast(double, d0) + __builtin_bit_cast(double, d1);
+    }
+}
+__device__ __forceinline__ float swapsum(float x, bool sixteen) {
+    int v = __builtin_bit_cast(int, x);
+    auto a = sixteen ? __builtin_amdgcn_permlane16_swap(v, v, false, false)
+                     : __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __builtin_bit_cast(float, (int)a[0]) + __builtin_bit_cast(float, (int)a[1]);
+}
+// Sum over the 4 lanes {l%16 + 16k}; the four lanes get the same bits (each
+// stage adds the same two operands in the same order).
+template <typename T>
+__device__ __forceinline__ T sum4(T x) {
+    return swapsum(swapsum(x, true), false);
+}
+// Value of lane J of this lane's 16-lane row (DPP row_newbcast).
+// Every lane is written, so no old value is needed.
+template <int J>
+__device__ __forceinline__ double bcast16(double x) {
+    long long v = __builtin_bit_cast(long long, x);
+    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, v);
+}
+template <int J>
+__device__ __forceinline__ float bcast16(float x) {
+    int v = __builtin_bit_cast(int, x);
+    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);
+    return __builtin_bit_cast(float, v);
+}
+// Value of lane L (wave-uniform).
+template <int L>
+__device__ __forceinline__ double rdlane(double x) {
+    struct P { int lo, hi; };
+    P p = __builtin_bit_cast(P, x);
+    p.lo = __builtin_amdgcn_readlane(p.lo, L);
+    p.hi = __builtin_amdgcn_readlane(p.hi, L);
+    return __builtin_bit_cast(double, p);
+}
+template <int L>
+__device__ __forceinline__ float rdlane(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), L));
+}
+
+// The lane id and n, made opaque to the optimiser.  The sweep is fully
+// unrolled; without this the compiler hoists every column's lane masks and
+// bounds out of the sweep and runs out of scalar registers holding them.
+__device__ __forceinline__ int lane_id() {
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+__device__ __forceinline__ int opaque_s(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Order this wave's LDS (and global) accesses across its lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Householder scalars from alpha and sigma^2 = ||tail||^2 (valid for
+// sigma^2 > 0; the caller replaces them when sigma^2 == 0):
+// nrm = sqrt(alpha^2 + sigma^2), beta = -sign(alpha) nrm (sign(0) = +1),
+// tau = (beta - alpha)/beta = 1 + |alpha|/nrm, scale = 1/(alpha - beta).
+// Hardware reciprocal / reciprocal square root refined by Newton steps.
+__device__ __forceinline__ void hh_scalars(double alpha, double sigma2, double& beta, double& tau, double& scale) {
+    const double s = fma(alpha, alpha, sigma2);
+    double y = __builtin_amdgcn_rsq(s);
+    double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    double nrm = s * y;
+    nrm = fma(fma(-nrm, nrm, s), 0.5 * y, nrm);
+    const double aa = fabs(alpha);
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    tau = fma(aa, y, 1.0);
+    const double d = aa + nrm;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    scale = (alpha >= 0.0) ? r : -r;
+}
+__device__ __forceinline__ void hh_scalars(float alpha, float sigma2, float& beta, float& tau, float& scale) {
+    const float s = fmaf(alpha, alpha, sigma2);
+    float y = __builtin_amdgcn_rsqf(s);
+    y = fmaf(0.5f * y, fmaf(-s * y, y, 1.0f), y);
+    float nrm = s * y;
+    nrm = fmaf(fmaf(-nrm, nrm, s), 0.5f * y, nrm);
+    const float aa = fabsf(alpha);
+    beta = (alpha >= 0.0f) ? -nrm : nrm;
+    tau = fmaf(aa, y, 1.0f);
+    const float d = aa + nrm;
+    float r = __builtin_amdgcn_rcpf(d);
+    r = fmaf(r, fmaf(-d, r, 1.0f), r);
+    scale = (alpha >= 0.0f) ? r : -r;
+}
+
+// ---- per-wave LDS -------------------------------------------------------------
+template <typename T, int NP>
+struct WSmem {
+    static constexpr int NCP = 16 * NP;
+    T R[NCP * (NCP + 1) / 2];  // on-chip R, upper triangle packed by rows
+    T scr[16][17];             // transposes and T staging
+};
+// Packed index of R[r][c], c >= r, rows of length NCP.
+template <int NCP>
+__device__ __forceinline__ int rpi(int r, int c) {
+    return r * NCP - ((r * (r - 1)) >> 1) + (c - r);
+}
+
+// Entry of a reflector as a matrix operand when the heads lie in the tile:
+// zero above the head row, one on it.
+template <typename T>
+__device__ __forceinline__ T vmask(T x, int r, int c) {
+    return (r > c) ? x : ((r == c) ? T(1) : T(0));
+}
+
+// Packed-T index of T[i][j], i <= j (column by column).
+__device__ __forceinline__ int64_t tpi(int i, int j) { return (int64_t)j * (j + 1) / 2 + i; }
+
+// ---- the block factorisation -----------------------------------------------------
+//
+// After the panels, emit() is called while the tile still holds the final
+// reflectors (it stores them); the off-diagonal blocks of T follow from
+// registers, so the tile's registers are free again by then.
+template <typename T, int NP, int SG, int MODE, typename Emit>
+__device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, const int n_, T* __restrict__ Tout,
+                                           T* __restrict__ tauout, Emit&& emit) {
+    typedef Mfma<T> M;
+    typedef typename M::acc acc_t;
+    constexpr int NCP = 16 * NP;
+
+    sfor<0, NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int c0 = 16 * p;
+        const int n = opaque_s(n_);
+        if (c0 >= n) return;
+        const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+        // live row groups of this panel
+        constexpr int S0 = (MODE == 0) ? p : 0;
+        constexpr int S1 = (MODE == 2) ? p + 1 : SG;
+        const int c = c0 + l16;
+        T sc_lane = T(1), tau_lane = T(0);
+
+        // ------------------------------------------------------ column sweep
+        sfor<0, 16>([&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            // Columns j >= n are not skipped: they are zero, so the arithmetic
+            // below leaves the tile unchanged (sigma^2 = 0, tau = 0, coef = 0)
+            // and no value has to be merged across a branch.
+            const int n = opaque_s(n_);
+            const int j = c0 + jj;
+            const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+            __builtin_amdgcn_sched_barrier(0);
+            const int c = c0 + l16;
+            constexpr int hreg = M::row_reg(jj), hl4 = M::row_l4(jj);
+            T alpha, hc;
+            if constexpr (MODE == 0) {
+                const T hv = x[p][hreg][p];
+                alpha = rdlane<16 * hl4 + jj>(hv);
+                hc = sum4((l4 == hl4) ? hv : T(0));
+            } else {
+                alpha = sm.R[rpi<NCP>(j, j)];
+                const T hr = sm.R[rpi<NCP>(j, (c > j) ? c : j)];
+                hc = (c > j && c < n) ? hr : T(0);
+            }
+            // column j, broadcast to the lanes of the other columns (tail rows only)
+            T xj[SG][4];
+            T a0 = T(0), a1 = T(0);
+            sfor<S0, S1>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    T v = bcast16<jj>(x[s][i][p]);
+                    if constexpr (MODE == 0 && s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
+                    xj[s][i] = v;
+                    if (i & 1) a1 = fma(v, x[s][i][p], a1);
+                    else a0 = fma(v, x[s][i][p], a0);
+                }
+            });
+            const T g = sum4(a0 + a1);
+            const T sigma2 = bcast16<jj>(g);
+            T beta, tau, scale;
+            hh_scalars(alpha, sigma2, beta, tau, scale);
+            const bool zt = (sigma2 == T(0));
+            tau = zt ? T(0) : tau;
+            scale = zt ? T(0) : scale;
+            beta = zt ? alpha : beta;
+            const T w = fma(scale, g, hc);
+            const bool trail = (c > j) && (c < n);
+            const T tw = tau * w;
+            const T coef = trail ? -tw * scale : T(0);
+            if constexpr (MODE != 0) {
+                if (l4 == 0 && c >= j && c < n) sm.R[rpi<NCP>(j, (c > j) ? c : j)] = (c == j) ? beta : hc - tw;
+            }
+            sfor<S0, S1>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[s][i][p] = fma(xj[s][i], coef, x[s][i][p]);
+            });
+            if constexpr (MODE == 0) {
+                T& hv = x[p][hreg][p];
+                const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);
+                hv = (l4 == hl4) ? nh : hv;
+            }
+            // lane jj keeps its column unscaled until the panel ends (sc_lane)
+            sc_lane = (l16 == jj) ? scale : sc_lane;
+            tau_lane = (l16 == jj) ? tau : tau_lane;
+            // in-panel Gram P[c][j] = v_c^T v_j (lanes c < j) and column j of the
+            // panel's T (row l16 per lane group, kept in sm.scr):
+            // T[a][j] = -tau_j sum_{k<j} T[a][k] P[k][j], T[j][j] = tau_j
+            const T pw = sc_lane * w;
+            T t = T(0);
+            sfor<0, jj>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                t = fma(sm.scr[l16][k], bcast16<k>(pw), t);
+            });
+            if (l4 == 0) sm.scr[l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
+        });
+
+        // reflector tails: scale the panel's columns (delayed from the sweep)
+        sfor<S0, S1>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (MODE == 0 && s == p)
+                    x[s][i][p] = (M::orow(l4, i) > l16) ? x[s][i][p] * sc_lane : x[s][i][p];
+                else
+                    x[s][i][p] *= sc_lane;
+            }
+        });
+        if (l4 == 0 && c < n) tauout[c] = tau_lane;
+
+        // diagonal T block in the MFMA D layout; to global
+        wave_sync();
+        T tpp[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tpp[r] = sm.scr[M::orow(l4, r)][l16];
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = c0 + M::orow(l4, r);
+            if (i <= c && c < n) Tout[tpi(i, c)] = tpp[r];
+        }
+        if constexpr (p + 1 < NP) {
+            {
+                // ---------------------------------------------- W = V_p^T X (trailing tiles)
+                acc_t w0[NP];
+                sfor<p + 1, NP>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    w0[q] = acc_t{0, 0, 0, 0};
+                    if constexpr (MODE != 0) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = c0 + M::orow(l4, r), cc = 16 * q + l16;
+                            const T v = sm.R[rpi<NCP>(i, cc)];
+                            w0[q][r] = (i < n && cc < n) ? v : T(0);
+                        }
+                    }
+                });
+                sfor<S0, S1>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        T a = x[s][i][p];
+                        if constexpr (MODE == 0 && s == p) a = vmask(a, M::orow(l4, i), l16);
+                        sfor<p + 1, NP>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            w0[q] = M::mma(a, x[s][i][q], w0[q]);
+                        });
+                    }
+                });
+                // ---------------------------------------------- -W' = -T_pp^T W; R rows
+                T ntpp[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ntpp[r] = -tpp[r];
+                acc_t nw[NP];
+                sfor<p + 1, NP>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    nw[q] = acc_t{0, 0, 0, 0};
+                });
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    sfor<p + 1, NP>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        nw[q] = M::mma(ntpp[kc], w0[q][kc], nw[q]);
+                    });
+                }
+                if constexpr (MODE != 0) {
+                    sfor<p + 1, NP>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = c0 + M::orow(l4, r), cc = 16 * q + l16;
+                            if (i < n && cc < n) sm.R[rpi<NCP>(i, cc)] += nw[q][r];
+                        }
+                    });
+                }
+                // ---------------------------------------------- X -= V_p W'
+                sfor<S0, S1>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        T v = x[s][i][p];
+                        if constexpr (MODE == 0 && s == p) v = vmask(v, M::orow(l4, i), l16);
+                        sm.scr[M::orow(l4, i)][l16] = v;
+                    }
+                    wave_sync();
+                    T vt[4];
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) vt[kc] = sm.scr[l16][M::orow(l4, kc)];
+                    wave_sync();
+                    acc_t u[NP];
+                    sfor<p + 1, NP>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        u[q] = acc_t{x[s][0][q], x[s][1][q], x[s][2][q], x[s][3][q]};
+                    });
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) {
+                        sfor<p + 1, NP>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            u[q] = M::mma(vt[kc], nw[q][kc], u[q]);
+                        });
+                    }
+                    sfor<p + 1, NP>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) x[s][r][q] = u[q][r];
+                    });
+                });
+            }
+        }
+    });
+
+    const int n = opaque_s(n_);
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    if constexpr (MODE == 0) {
+        // R of the block: the upper triangle of its first n rows
+        sfor<0, (SG < NP ? SG : NP)>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * s + M::orow(l4, i);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int cc = 16 * q + l16;
+                    if (r < n && cc >= r && cc < n) sm.R[rpi<NCP>(r, cc)] = x[s][i][q];
+                }
+            }
+        });
+    }
+
+    if constexpr (NP == 1) {
+        emit();
+    } else {
+        // ------------------------------------------------------ T blocks above the diagonal
+        // Gram blocks P_ac = V_a^T V_c (a < c), from MFMA(V_c, V_a): the result
+        // is P_ac in the A-operand layout.  Rows where V_c or V_a vanishes are
+        // skipped: above panel c's heads in the first block, below panel a's
+        // rows in a tree node.
+        acc_t P[NP][NP];
+        sfor<1, NP>([&](auto cc_) {
+            constexpr int cq = decltype(cc_)::value;
+            sfor<0, cq>([&](auto ac_) {
+                constexpr int a = decltype(ac_)::value;
+                P[a][cq] = acc_t{0, 0, 0, 0};
+            });
+        });
+        sfor<0, SG>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sfor<1, NP>([&](auto cc_) {
+                    constexpr int cq = decltype(cc_)::value;
+                    sfor<0, cq>([&](auto ac_) {
+                        constexpr int a = decltype(ac_)::value;
+                        constexpr bool live = (MODE == 0) ? (s >= cq) : ((MODE == 2) ? (s <= a) : true);
+                        if constexpr (live) {
+                            T vc = x[s][i][cq];
+                            if constexpr (MODE == 0 && s == cq) vc = vmask(vc, M::orow(l4, i), l16);
+                            P[a][cq] = M::mma(vc, x[s][i][a], P[a][cq]);
+                        }
+                    });
+                });
+            }
+        });
+        emit();
+        // diagonal blocks back from this wave's stores: D layout (tD) and
+        // A-operand layout (tA)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        T tD[NP][4], tA[NP][4];
+        sfor<0, NP>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = M::orow(l4, r);
+                tD[b][r] = (o <= l16 && 16 * b + l16 < n) ? Tout[tpi(16 * b + o, 16 * b + l16)] : T(0);
+                tA[b][r] = (l16 <= o && 16 * b + o < n) ? Tout[tpi(16 * b + l16, 16 * b + o)] : T(0);
+            }
+        });
+        // T_ab = -T_aa sum_{c=a+1..b} P_ac T_cb, a = b-1 .. 0
+        sfor<1, NP>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            {
+                acc_t tcb[NP];
+                tcb[b] = acc_t{tD[b][0], tD[b][1], tD[b][2], tD[b][3]};
+                sfor<0, b>([&](auto ar) {
+                    constexpr int a = b - 1 - decltype(ar)::value;
+                    acc_t y = acc_t{0, 0, 0, 0};
+                    sfor<a + 1, b + 1>([&](auto cc_) {
+                        constexpr int cq = decltype(cc_)::value;
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P[a][cq][kc], tcb[cq][kc], y);
+                    });
+                    acc_t t = acc_t{0, 0, 0, 0};
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) t = M::mma(tA[a][kc], y[kc], t);
+                    tcb[a] = -t;
+                    const int jx = 16 * b + l16;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (jx < n) Tout[tpi(16 * a + M::orow(l4, r), jx)] = tcb[a][r];
+                });
+            }
+        });
+    }
+    wave_sync();
+}
+
+// ---- tile I/O -------------------------------------------------------------------
+// Row 16s + orow(l4, i) of the tile is the lane's base row orow(l4, 0) plus a
+// lane-independent offset, so a full tile needs one per-lane pointer; a
+// partial tile (last block of a chain, n < NCP) takes the masked path.
+template <typename T, int NP, int SG>
+__device__ __forceinline__ void wload(T (&x)[SG][4][NP], const T* __restrict__ A, int64_t lda, int64_t r0, int rows,
+                                      int n) {
+    typedef Mfma<T> M;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    if (rows == 16 * SG && n == 16 * NP) {
+        const T* __restrict__ pb = A + (r0 + M::orow(l4, 0)) * lda + l16;
+#pragma unroll
+        for (int s = 0; s < SG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T* __restrict__ pr = pb + (int64_t)(16 * s + M::orow(0, i) - M::orow(0, 0)) * lda;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) x[s][i][q] = pr[16 * q];
+            }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * s + M::orow(l4, i);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int cc = 16 * q + l16;
+                x[s][i][q] = (r < rows && cc < n) ? A[(r0 + r) * lda + cc] : T(0);
+            }
+        }
+}
+
+template <typename T, int NP, int SG>
+__device__ __forceinline__ void wstore(const T (&x)[SG][4][NP], T* __restrict__ A, int64_t lda, int64_t r0, int rows,
+                                       int n) {
+    typedef Mfma<T> M;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    if (rows == 16 * SG && n == 16 * NP) {
+        T* __restrict__ pb = A + (r0 + M::orow(l4, 0)) * lda + l16;
+#pragma unroll
+        for (int s = 0; s < SG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                T* __restrict__ pr = pb + (int64_t)(16 * s + M::orow(0, i) - M::orow(0, 0)) * lda;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) pr[16 * q] = x[s][i][q];
+            }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * s + M::orow(l4, i);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int cc = 16 * q + l16;
+                if (r < rows && cc < n) A[(r0 + r) * lda + cc] = x[s][i][q];
+            }
+        }
+}
+
+// R (LDS, packed) -> row-major n x n with zeros below the diagonal (lane =
+// column, one row per step).
+template <typename T, int NP>
+__device__ __forceinline__ void r_out(const WSmem<T, NP>& sm, int n, T* __restrict__ R, int64_t ldr, bool lower) {
+    constexpr int NCP = 16 * NP;
+    const int j = lane_id();
+    for (int i = 0; i < n; ++i) {
+        if (j < n && (j >= i || lower)) R[i * ldr + j] = (j >= i) ? sm.R[rpi<NCP>(i, j >= i ? j : i)] : T(0);
+    }
+}
+// Row-major R (upper part) -> LDS.
+template <typename T, int NP>
+__device__ __forceinline__ void r_in(WSmem<T, NP>& sm, int n, const T* __restrict__ R) {
+    constexpr int NCP = 16 * NP;
+    const int j = lane_id();
+    for (int i = 0; i < n; ++i) {
+        if (j < n && j >= i) sm.R[rpi<NCP>(i, j)] = R[i * n + j];
+    }
+    wave_sync();
+}
+
+// ---- one chain, then the tree nodes this wave completes -----------------------------
+//
+// Tree (Sec. 2.1; any tree shape gives a valid QR): level lev has stride
+// a^(lev-1); the node at i0 (a multiple of a*stride) folds its children
+// i0 + t*stride (t = 1..a-1, < W) into child i0.  Each chain, or node result,
+// is published in Rbuf; the wave that completes a node's last child (an
+// atomic count per node, zeroed before the launch) performs the node, so no
+// wave waits for another and the levels need no separate launches.  The node
+// arithmetic does not depend on which child arrived last.
+struct TreeArgs {
+    int* cnt;        // W * levels counters, zero at launch
+    void* Rout;      // final R (row-major, ldr), or null
+    int64_t ldr;
+    int zero_lower;  // also write zeros below R's diagonal
+};
+
+template <typename T, int NP, int SG>
+__device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ A, int64_t lda,
+                                          T* __restrict__ tau_blk, T* __restrict__ T_blk, T* __restrict__ Rbuf,
+                                          T* __restrict__ Ynode, T* __restrict__ Tnode, T* __restrict__ tau_node,
+                                          const TreeArgs& ta) {
+    const int n = (int)g.n;
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    const int64_t nn = (int64_t)n * n;
+    // R starts at zero, so its entries beyond column n stay zero
+    for (int e = lane_id(); e < (int)(sizeof(sm.R) / sizeof(T)); e += 64) sm.R[e] = T(0);
+    wave_sync();
+    // ---- the chain (flat tree)
+    {
+        const int64_t start = chain_start(g, c), end = chain_end(g, c);
+        const int nb = chain_nblocks(g, c);
+        const int64_t blk0 = chain_blk0(g, c);
+        constexpr int H = 16 * SG;
+        for (int b = 0; b < nb; ++b) {
+            const int64_t r0 = start + (int64_t)b * H;
+            const int rows = (int)((end - r0) < H ? (end - r0) : H);
+            T x[SG][4][NP];
+            wload<T, NP, SG>(x, A, lda, r0, rows, n);
+            auto emit = [&]() { wstore<T, NP, SG>(x, A, lda, r0, rows, n); };
+            if (b == 0)
+                wave_block<T, NP, SG, 0>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+            else
+                wave_block<T, NP, SG, 1>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+        }
+    }
+    // ---- the tree
+    int cur = c;
+    for (int lev = 1; lev <= g.levels; ++lev) {
+        const int64_t stride = ipow(g.arity, lev - 1);
+        const int64_t span = stride * g.arity;
+        const int i0 = (int)((cur / span) * span);
+        int nch = (int)((g.W - i0 + stride - 1) / stride);
+        if (nch > g.arity) nch = g.arity;
+        if (nch <= 1) continue;  // unpaired: carried up unchanged
+        r_out<T, NP>(sm, n, Rbuf + (int64_t)cur * nn, n, true);
+        __threadfence();
+        int old = 0;
+        if ((threadIdx.x & 63) == 0) old = atomicAdd(ta.cnt + (int64_t)(lev - 1) * g.W + i0, 1);
+        old = __builtin_amdgcn_readfirstlane(old);
+        if (old != nch - 1) return;
+        __threadfence();
+        if (cur != i0) r_in<T, NP>(sm, n, Rbuf + (int64_t)i0 * nn);
+        for (int t = 1; t < nch; ++t) {
+            const int64_t ch = i0 + t * stride;
+            T xc[NP][4][NP];
+            wload<T, NP, NP>(xc, Rbuf + ch * nn, n, 0, n, n);
+            auto emit = [&]() { wstore<T, NP, NP>(xc, Ynode + ch * nn, n, 0, n, n); };
+            wave_block<T, NP, NP, 2>(xc, sm, n, Tnode + ch * tri, tau_node + ch * n, emit);
+        }
+        cur = i0;
+    }
+    r_out<T, NP>(sm, n, Rbuf, n, true);
+    if (ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
+}
+
+}  // namespace tsqr

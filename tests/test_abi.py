@@ -72,9 +72,10 @@ def test_apply_argument_errors():
 
 
 @pytest.mark.parametrize("m,n,h,chains,arity", [
-    (4096, 16, 256, 0, 0), (1 << 20, 64, 256, 0, 0), (1000, 8, 64, 0, 3),
-    (300, 64, 256, 0, 0), (64, 64, 64, 0, 0), (129, 64, 64, 0, 0), (10000, 33, 128, 7, 4),
-    (65536 + 17, 32, 128, 100, 2),
+    (4096, 16, 64, 16, 0), (1 << 20, 64, 64, 0, 0), (1000, 8, 64, 0, 3),
+    (300, 64, 64, 0, 0), (64, 64, 64, 0, 0), (129, 64, 64, 0, 0), (10000, 33, 64, 7, 4),
+    (65536 + 17, 32, 64, 100, 2), (5000, 20, 64, 0, 2), (5000, 16, 64, 0, 5),
+    (1 << 24, 8, 64, 0, 2), (777, 1, 64, 3, 0),
 ])
 def test_plan_geometry_covers_rows(m, n, h, chains, arity):
     g = plan_geometry(m, n, block_rows=h, chains=chains, arity=arity)
@@ -91,15 +92,30 @@ def test_plan_geometry_covers_rows(m, n, h, chains, arity):
     assert g["padded_n"] in (8, 16, 32, 64) and g["padded_n"] >= n
 
 
-def test_plan_geometry_config1_is_binary_tree_over_256_row_blocks():
-    g = plan_geometry(4096, 16)
-    assert g["block_rows"] == 256 and g["chains"] == 16 and g["chain_rows"] == 256
+def test_plan_geometry_config1_is_binary_tree_over_256_row_leaves():
+    # leaves of 256 rows (chains of four 64-row blocks), binary tree
+    g = plan_geometry(4096, 16, chains=16)
+    assert g["block_rows"] == 64 and g["chains"] == 16 and g["chain_rows"] == 256
     assert g["arity"] == 2 and g["levels"] == 4
+
+
+def test_plan_geometry_default_block_rows():
+    # 64-row blocks; one wave per chain, 1024 chains at most by default
+    for n in (1, 9, 32, 64):
+        assert plan_geometry(1 << 20, n)["block_rows"] == 64
+    assert plan_geometry(1 << 20, 64)["chains"] == 1024
+    assert plan_geometry(1000, 64)["chains"] == 15
+
+
+def test_plan_geometry_rejects_other_block_heights():
+    for n, h in [(64, 128), (16, 256), (8, 32)]:
+        with pytest.raises(_lib.TsqrError):
+            plan_geometry(4096, n, block_rows=h)
 
 
 def test_plan_geometry_short_last_chain_merges():
     # 3 chains of 256 rows would leave 10 rows (< n = 16) for a fourth chain
-    g = plan_geometry(3 * 256 + 10, 16, block_rows=256, chains=4)
+    g = plan_geometry(3 * 256 + 10, 16, chains=4)
     assert g["chains"] == 3
     assert 3 * 256 + 10 - 2 * g["chain_rows"] >= 16
 
@@ -109,7 +125,7 @@ def test_implicit_q_parameter_count():
     mn - n(n+1)/2, when every leaf is n x n or taller: each leaf stores the
     below-diagonal part of its block, each tree step an upper triangle of a
     combined triangle."""
-    for (m, n, h) in [(4096, 16, 256), (1024, 8, 64), (2048, 64, 256)]:
+    for (m, n, h) in [(4096, 16, 64), (1024, 8, 64), (2048, 64, 64), (4096, 32, 64)]:
         g = plan_geometry(m, n, block_rows=h, chains=m // h)
         W = g["chains"]
         leaves = W * (h * n - n * (n + 1) // 2)

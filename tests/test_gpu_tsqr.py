@@ -99,11 +99,11 @@ def _check(A, B, g, o, rtol_r=1e-11, rtol_q=1e-11, inv=1e-13):
 
 
 def test_config1_4096x16_f64():
-    """4096 x 16, iid N(0,1) (seed 1), row blocks of 256, binary tree."""
+    """4096 x 16, iid N(0,1) (seed 1), leaves of 256 rows, binary tree."""
     _note("case: config1 4096x16 f64")
     A = workloads.cfg1()
     B = workloads.gaussian(4096, 5, 99)
-    out = _run(A, B, block_rows=256)
+    out = _run(A, B, chains=16)
     info = out["qt"].info()
     assert info["chains"] == 16 and info["levels"] == 4 and info["arity"] == 2
     g = _normalised(out["R"], out["Q"], out["QtB"])
@@ -117,15 +117,21 @@ SHAPES = [
     (100, 1, 64, 0, 0),
     (1000, 3, 64, 0, 0),
     (1000, 8, 64, 5, 3),
-    (777, 31, 128, 0, 0),
-    (2049, 32, 256, 0, 0),
-    (2500, 33, 128, 3, 2),
-    (5000, 64, 256, 0, 0),
-    (5000, 64, 128, 1, 0),
+    (777, 31, 64, 0, 0),
+    (2049, 32, 64, 0, 0),
+    (2500, 33, 64, 3, 2),
+    (5000, 64, 64, 0, 0),
+    (5000, 64, 64, 1, 0),
     (3333, 64, 64, 7, 4),
-    (20000, 16, 256, 10, 2),
-    (300, 64, 256, 0, 0),
+    (20000, 16, 64, 10, 2),
+    (300, 64, 64, 2, 3),
     (129, 64, 64, 0, 0),
+    (4100, 20, 64, 0, 2),
+    (70000, 64, 64, 0, 2),
+    (100000, 48, 64, 0, 3),
+    (3000, 12, 64, 0, 0),
+    (9999, 5, 64, 0, 7),
+    (262144 + 3, 17, 64, 0, 2),
 ]
 
 
@@ -145,7 +151,7 @@ def test_zero_column_and_zero_block():
     A = workloads.gaussian(3000, 16, 77)
     A[:, 5] = 0.0
     A[700:1500, :] = 0.0
-    out = _run(A, None, block_rows=128)
+    out = _run(A, None, chains=5)
     R = out["R"].cpu().numpy()
     Q = out["Q"].cpu().numpy()
     assert abs(R[5, 5]) == 0.0
@@ -195,8 +201,7 @@ def test_tree_shape_invariance():
     _note("case: tree shapes")
     A = workloads.gaussian(40000, 32, 8)
     Rs = []
-    for kw in [dict(block_rows=256), dict(block_rows=64, chains=1), dict(block_rows=128, chains=9, arity=3),
-               dict(block_rows=64, chains=625, arity=2)]:
+    for kw in [dict(), dict(chains=1), dict(chains=9, arity=3), dict(chains=625, arity=2), dict(chains=40, arity=5)]:
         out = _run(A, None, **kw)
         Rs.append(_normalised(out["R"], out["Q"])["R"])
     for R in Rs[1:]:
