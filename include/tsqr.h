@@ -57,13 +57,14 @@ extern "C" {
 typedef struct tsqr_qtree_s* tsqr_qtree;
 
 /* Tree shape.  0 in any field = the library default.
- *   block_rows : rows per block of the chain kernels: 64, 128 or 256
- *                (default 256).  Each block's reflectors carry one n x n T.
+ *   block_rows : rows per block of the chain kernels: 64 (the default and
+ *                the only value accepted).  Each block's reflectors carry one
+ *                n x n T.
  *   chains     : number of contiguous row ranges reduced independently with
  *                the flat tree of sequential TSQR (Sec. 2.1); their R
  *                factors are then reduced on the tree.  Default:
- *                min(number of blocks, 512).  chains = number of blocks gives
- *                the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
+ *                min(number of blocks, 1024).  chains = number of blocks
+ *                gives the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
  *   arity      : fan-in of the tree over the chain R factors (default 2).
  *   flags      : reserved, must be 0. */
 typedef struct tsqr_opts {
@@ -172,6 +173,49 @@ int tsqr_set_phase_events(int phase, void* start, void* stop);
 /* Last HIP error code seen by this thread (0 if none) and a message. */
 int tsqr_last_hip_error(void);
 const char* tsqr_status_string(int status);
+
+/* ---------------------------------------------------------------- batched
+ * Many independent TSQR factorisations (Sec. 2.1 for each matrix) of uneven
+ * shapes in one graph launch: the chains of all matrices form one work queue
+ * (longest first) served by persistent one-wave workers, and each matrix's
+ * tree nodes are performed by the worker that completes a node's last child.
+ * The tree shape of each matrix (chains, arity) is a per-matrix option; the
+ * Python autotuner chooses them per (dtype, column class, row range). */
+typedef struct tsqr_batch_s* tsqr_batch;
+
+/* Plan `count` factorisations.  m, n: HOST arrays of count entries with
+ *   m[i] >= n[i] >= 1 and n[i] <= 64.  opts: NULL (defaults for every
+ *   matrix) or a HOST array of count tsqr_opts (same meaning as for
+ *   tsqr_factor, 0 = default).  Allocates the device workspace of every tree
+ *   (owned by the plan, hipMalloc; the call synchronises the device) and a
+ *   stream used for graph capture.  Errors: -2 count < 1, -3/-4 null or bad
+ *   m/n entries (TSQR_ERR_UNSUPPORTED for n > 64), TSQR_ERR_NOMEM,
+ *   TSQR_ERR_HIP. */
+int tsqr_batch_plan_create(int dtype, int32_t count, const int64_t* m, const int64_t* n, const tsqr_opts* opts,
+                           tsqr_batch* plan_out);
+
+/* Factor every matrix of the plan on `stream`.
+ *   A, lda, R, ldr: DEVICE arrays of count entries.  A[i] is matrix i
+ *   (row-major, lda[i] >= n[i]), overwritten with its leaf reflectors; R[i]
+ *   receives its n x n R (row-major, ldr[i] >= n[i], zeros below the
+ *   diagonal) and may be NULL.  The four arrays are read by the device when
+ *   the work runs, so their contents may change between calls.
+ *   The first call captures a hipGraph (fill kernels that clear the work
+ *   queue and the node counters, then one persistent kernel per column
+ *   class 1..16, 17..32, 33..64) and launches it on `stream`; later calls
+ *   with the same four array addresses only launch the graph again, other
+ *   addresses capture a new one.  Calls on one plan must not overlap in time
+ *   (they share the plan's workspace and counters). */
+int tsqr_batch_factor(tsqr_batch plan, void* const* A, const int64_t* lda, void* const* R, const int64_t* ldr,
+                      void* stream);
+
+/* out[0] count, out[1] total chains, out[2] column classes launched,
+ * out[3] workspace bytes, out[4] 1 if a graph is captured, out[5] persistent
+ * workers launched over all classes.  out: host array of 6. */
+int tsqr_batch_plan_info(tsqr_batch plan, int64_t* out);
+
+/* Release the plan (synchronises the device first).  NULL is accepted. */
+int tsqr_batch_plan_destroy(tsqr_batch plan);
 
 #ifdef __cplusplus
 }

@@ -74,6 +74,10 @@ def load():
         "tsqr_copy_r": [i32, i64, vp, i64, vp, i64, vp],
         "tsqr_backward": [i32, i64, i64, i64, vp, i64, i64, vp, i64, i64, vp, i64, i64, vp, i64, i64,
                           vp, i64, i64, vp],
+        "tsqr_batch_plan_create": [i32, ctypes.c_int32, p64, p64, popts, ctypes.POINTER(vp)],
+        "tsqr_batch_factor": [vp, vp, vp, vp, vp, vp],
+        "tsqr_batch_plan_info": [vp, p64],
+        "tsqr_batch_plan_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

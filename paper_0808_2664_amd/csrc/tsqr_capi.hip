@@ -52,6 +52,13 @@ constexpr int64_t kDefaultChains = 1024;
 // Tree geometry for (m, n): chains of whole blocks, the last chain absorbing
 // a remainder too short to hold an n x n leaf (a chain's first block must hold
 // n rows: its R is an n x n triangle).
+int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g);
+
+int make_geom_opts(int64_t m, int64_t n, const GeomOpts& go, Geom* g) {
+    tsqr_opts o{go.block_rows, go.chains, go.arity, go.flags};
+    return make_geom(m, n, &o, g);
+}
+
 int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     if (n < 1 || n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     if (m < n) return -1;

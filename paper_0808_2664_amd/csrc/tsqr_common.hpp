@@ -82,6 +82,14 @@ inline void phase_end(int p, hipStream_t st) {
 // (row-major, ldr; zeros below the diagonal when zero_lower; R may be null).
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
                          bool zero_lower, hipStream_t st);
+// Host-side geometry and workspace layout (tsqr_capi.hip).
+struct GeomOpts {
+    int block_rows = 0, chains = 0, arity = 0, flags = 0;
+};
+int make_geom_opts(int64_t m, int64_t n, const GeomOpts& o, Geom* g);
+size_t work_bytes(const Geom& g, bool f64);
+void work_carve(Work* w, const Geom& g, bool f64);
+
 // Block shapes of the factor kernel: rows per block h for NC padded columns.
 bool wave_shape_ok(int NC, int h);
 int wave_default_h(int NC);

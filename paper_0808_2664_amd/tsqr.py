@@ -217,3 +217,79 @@ class TSQRFunction(torch.autograd.Function):
 def tsqr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
     """Differentiable thin QR (Q, R) with diag(R) >= 0."""
     return TSQRFunction.apply(A, block_rows, chains, arity)
+
+
+class BatchPlan:
+    """Batched TSQR of many uneven matrices in one graph launch.
+
+    shapes: list of (m, n); opts: None (library defaults) or a list of
+    (chains, arity) per matrix (0 = default), e.g. from
+    ``autotune.choose_batch``.  The device arrays of matrix pointers and
+    leading dimensions live in the plan, so repeated ``factor`` calls replay
+    the same captured graph with new matrices.
+    """
+
+    def __init__(self, shapes, dtype=torch.float64, opts=None, device="cuda"):
+        lib = _lib.load()
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.count = len(self.shapes)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        code = _lib.TSQR_F64 if dtype == torch.float64 else _lib.TSQR_F32
+        ms = (ctypes.c_int64 * self.count)(*[m for m, _ in self.shapes])
+        ns = (ctypes.c_int64 * self.count)(*[n for _, n in self.shapes])
+        popts = None
+        if opts is not None:
+            arr = (_lib.TsqrOpts * self.count)()
+            for i, (chains, arity) in enumerate(opts):
+                arr[i] = _lib.opts(0, int(chains), int(arity))
+            popts = arr
+        self._h = ctypes.c_void_p()
+        _lib.check("tsqr_batch_plan_create", lib.tsqr_batch_plan_create(code, self.count, ms, ns, popts,
+                                                                         ctypes.byref(self._h)))
+        # device argument arrays (stable addresses for graph replay)
+        self._dA = torch.zeros(self.count, dtype=torch.int64, device=self.device)
+        self._dlda = torch.zeros(self.count, dtype=torch.int64, device=self.device)
+        self._dR = torch.zeros(self.count, dtype=torch.int64, device=self.device)
+        self._dldr = torch.zeros(self.count, dtype=torch.int64, device=self.device)
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 6)()
+        _lib.check("tsqr_batch_plan_info", _lib.load().tsqr_batch_plan_info(self._h, out))
+        keys = ("count", "chains", "classes", "workspace_bytes", "graph_captured", "workers")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def factor(self, As, Rs=None):
+        """Factor the matrices As (list of device tensors, in place: each is
+        overwritten with its reflectors).  Returns the list of R factors
+        (n x n, diag(R) with the Householder signs)."""
+        if len(As) != self.count:
+            raise ValueError("expected %d matrices" % self.count)
+        if Rs is None:
+            Rs = [torch.empty(n, n, dtype=self.dtype, device=self.device) for _, n in self.shapes]
+        for A, (m, n) in zip(As, self.shapes):
+            if A.shape != (m, n) or A.dtype != self.dtype:
+                raise ValueError("matrix shape/dtype does not match the plan")
+        ha = torch.tensor([A.data_ptr() for A in As], dtype=torch.int64)
+        hl = torch.tensor([_ld(A) for A in As], dtype=torch.int64)
+        hr = torch.tensor([R.data_ptr() for R in Rs], dtype=torch.int64)
+        hlr = torch.tensor([_ld(R) for R in Rs], dtype=torch.int64)
+        self._dA.copy_(ha)
+        self._dlda.copy_(hl)
+        self._dR.copy_(hr)
+        self._dldr.copy_(hlr)
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _lib.check("tsqr_batch_factor", _lib.load().tsqr_batch_factor(
+            self._h, _ptr(self._dA), _ptr(self._dlda), _ptr(self._dR), _ptr(self._dldr), st))
+        return Rs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().tsqr_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -99,3 +99,13 @@ def cfg5_batch(batch: int = 256, m: int = 8192, n: int = 32):
 def fd_case(m: int = 1024, n: int = 8):
     """Finite-difference check case (seed 11)."""
     return gaussian(m, n, 11)
+
+
+def cfg4_device_matrix(i: int, m: int, n: int, seed: int = 6, dtype=None, device="cuda"):
+    """Matrix i of the batch generated on the device (iid N(0,1), torch's
+    Philox generator seeded by seed * 1000003 + i): the full 2000-matrix batch
+    (about 16 GB in FP64) is drawn on the GPU; tests copy the matrices they
+    check back to the host."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(seed * 1000003 + i)
+    return torch.randn(m, n, dtype=dtype or torch.float64, device=device, generator=g)
