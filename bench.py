@@ -32,7 +32,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector / matrix, published
 METRIC = "TSQR/CAQR GFLOP/s + HBM GB/s vs roofline; batched & fwd+bwd vs plain"
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_chain_factor_2p20x64_f64.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0808_2664_amd", "csrc", "tsqr_factor.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_0808_2664_amd", "csrc", f)
+              for f in ("tsqr_factor.hip", "tsqr_wave.hpp", "tsqr_common.hpp")]
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector / matrix, published
 
 
 def parse():
@@ -48,6 +50,8 @@ def parse():
     p.add_argument("--arity", type=int, default=0)
     p.add_argument("--cpu-rows", type=int, default=1 << 19,
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the batched, CAQR and forward+backward measurements")
     return p.parse_args()
 
 
@@ -62,9 +66,12 @@ def bytes_alg(m, n, k, es=8):
     return 2.0 * es * m * n, es * (m * n + 2.0 * m * k), 2.0 * es * m * n
 
 
-def src_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def src_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(m, n):
@@ -198,12 +205,18 @@ def main():
     traffic = traffic_from_profile(m, n)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_chain_factor (TSQR leaves: flat tree per chain)",
+            "kernel": "k_wave_tsqr (chains and tree of one TSQR, one launch)",
             "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": by[0]}
     cpu = None
     if a.cpu_rows > 0:
         print("bench: oracle cpu baseline on %d rows" % a.cpu_rows, file=sys.stderr, flush=True)
         cpu = cpu_baseline(min(a.cpu_rows, m), n, k)
+    extras = {}
+    if not a.no_extras:
+        for name, fn in (("batched", bench_batched), ("caqr", bench_caqr), ("fwd_bwd", bench_fwd_bwd)):
+            print("bench: %s" % name, file=sys.stderr, flush=True)
+            extras[name] = fn(tq, torch, np)
+            torch.cuda.empty_cache()
     names = ("factor", "apply_qt", "form_q")
     phases = {}
     for p, nm in enumerate(names):
@@ -234,7 +247,162 @@ def main():
         "orthogonality": orth,
         "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
     }
+    out.update(extras)
     print(json.dumps(out))
+
+
+def _ev_ms(torch, fn, reps):
+    """Median over reps of fn() timed with events on the current stream."""
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
+def bench_batched(tq, torch, np):
+    """Config 4: 2000 matrices, m ~ U{512..65536}, n in {8,16,32,64}, one graph
+    launch with autotuned tree shapes, against 2000 sequential tsqr_factor
+    calls; FP64 and FP32.  Inputs are drawn on the device (seed 6)."""
+    import oracle
+    import workloads
+    from paper_0808_2664_amd import autotune
+    shapes = workloads.cfg4_shapes()
+    res = {"workload": "2000 matrices, m ~ U{512..65536}, n in {8,16,32,64}, iid N(0,1) (seed 6)"}
+    for dt, name, es in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+        src = [workloads.cfg4_device_matrix(i, m, n, dtype=dt) for i, (m, n) in enumerate(shapes)]
+        work = [x.clone() for x in src]
+        alg = sum(2.0 * es * m * n for m, n in shapes)
+        plan = tq.BatchPlan(shapes, dt, opts=autotune.choose_batch(shapes, dt))
+        Rs = plan.factor(work)
+        torch.cuda.synchronize()
+
+        def run_batched():
+            plan.factor(work)
+
+        def reset():
+            for w, x in zip(work, src):
+                w.copy_(x)
+        ts = []
+        for _ in range(3):
+            reset()
+            torch.cuda.synchronize()
+            ts.append(_ev_ms(torch, run_batched, 1))
+        t_b = sorted(ts)[1]
+        reset()
+        torch.cuda.synchronize()
+
+        def run_seq():
+            for w in work:
+                R, qt = tq.factor(w)
+                qt.close()
+        t_s = _ev_ms(torch, run_seq, 1)
+        # worst R error against the oracle on a sample (smallest, largest, an n = 64 one)
+        reset()
+        Rs = plan.factor(work)
+        torch.cuda.synchronize()
+        ms_ = np.array([m for m, _ in shapes])
+        sample = sorted({int(ms_.argmin()), int(ms_.argmax()), next(i for i, s in enumerate(shapes) if s[1] == 64)})
+        worst = 0.0
+        for i in sample:
+            R = Rs[i].double().cpu().numpy()
+            Ro = oracle.qr(src[i].double().cpu().numpy())[1]
+            worst = max(worst, oracle.rel_err(R * oracle.signs(R)[:, None], Ro))
+        gbs = alg / (t_b / 1e3) / 1e9
+        res[name] = {"ms": round(t_b, 3), "alg_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                     "sequential_ms": round(t_s, 3), "speedup_vs_sequential": round(t_s / t_b, 2),
+                     "worst_sampled_R_error": worst, "sample": sample, "plan": plan.info()}
+        plan.close()
+        del src, work
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_caqr(tq, torch, np):
+    """Config 3: CAQR of a 16384 x 16384 N(0,1) matrix (seed 5, drawn on the
+    device), panel 64, trailing updates in FP64 and in FP32 (FP32 MFMA, FP64
+    storage).  Backward error ||A - QR||/||A|| through the GPU's implicit Q."""
+    N = 16384
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A0 = torch.randn(N, N, dtype=torch.float64, device="cuda", generator=g)
+    fl = 4.0 * N ** 3 / 3.0
+    res = {"workload": "CAQR 16384 x 16384 FP64 storage, panel 64", "flops": fl}
+    R64 = None
+    for name, upd, peak in (("f64_update", torch.float64, FP64_PEAK_TFLOPS), ("f32_update", torch.float32,
+                                                                               FP32_PEAK_TFLOPS)):
+        A = A0.clone()
+        box = {}
+
+        def run():
+            A.copy_(A0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            box["R"], box["qt"] = tq.caqr(A, panel=64, update=upd)
+            e1.record()
+            torch.cuda.synchronize()
+            box["ms"] = e0.elapsed_time(e1)
+        run()
+        box["qt"].close()
+        ts = []
+        for _ in range(2):
+            run()
+            ts.append(box["ms"])
+            if len(ts) < 2:
+                box["qt"].close()
+        ms = min(ts)
+        R, qt = box["R"], box["qt"]
+        X = torch.zeros(N, N, dtype=torch.float64, device="cuda")
+        X.copy_(torch.triu(R))
+        qt.apply_q(X)
+        be = (torch.linalg.norm(X - A0) / torch.linalg.norm(A0)).item()
+        qt.close()
+        del X
+        tfl = fl / (ms / 1e3) / 1e12
+        ent = {"ms": round(ms, 2), "tflops": round(tfl, 2), "frac_peak": round(tfl / peak, 4),
+               "peak_tflops": peak, "backward_error": be}
+        Rn = R * torch.sign(torch.where(torch.diagonal(R) == 0, torch.ones_like(torch.diagonal(R)),
+                                        torch.diagonal(R)))[:, None]
+        if R64 is None:
+            R64 = Rn
+        else:
+            ent["R_error_vs_f64_update"] = (torch.linalg.norm(Rn - R64) / torch.linalg.norm(R64)).item()
+        res[name] = ent
+        del A, R
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_fwd_bwd(tq, torch, np):
+    """Config 5: differentiable TSQR of 262144 x 32 FP64 (seed 7; dQ, dR seeds
+    8, 9): forward alone against forward + backward."""
+    import workloads
+    A_np, dQ_np, dR_np = workloads.cfg5()
+    A = torch.from_numpy(A_np).cuda()
+    dQ = torch.from_numpy(dQ_np).cuda()
+    dR = torch.from_numpy(dR_np).cuda()
+
+    def fwd():
+        tq.tsqr(A)
+
+    Ag = A.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        Q, R = tq.tsqr(Ag)
+        torch.autograd.backward((Q, R), (dQ, dR))
+    for f in (fwd, fwd_bwd):
+        f()
+    t_f = _ev_ms(torch, fwd, 5)
+    t_fb = _ev_ms(torch, fwd_bwd, 5)
+    m, n = A.shape
+    # HBM words: forward reads A, writes Y, reads Y, writes Q; backward reads Q, R, dQ, writes dA
+    fb_bytes = 8.0 * m * n * (4 + 3)
+    return {"workload": "TSQR forward (factor + Q) and backward (QR adjoint), 262144 x 32 FP64",
+            "fwd_ms": round(t_f, 4), "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3),
+            "fwd_bwd_alg_gbs": round(fb_bytes / (t_fb / 1e3) / 1e9, 1)}
 
 
 def ctypes_ptr(event):
