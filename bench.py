@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector / matrix, published
 METRIC = "TSQR/CAQR GFLOP/s + HBM GB/s vs roofline; batched & fwd+bwd vs plain"
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_chain_factor_2p20x64_f64.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_wave_tsqr_2p20x64_f64.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_0808_2664_amd", "csrc", f)
               for f in ("tsqr_factor.hip", "tsqr_wave.hpp", "tsqr_common.hpp")]
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector / matrix, published
