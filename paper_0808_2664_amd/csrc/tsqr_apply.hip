@@ -166,6 +166,228 @@ __device__ __forceinline__ void apply_block(ApplySmem<S, C, NC>& sm, int n, cons
     __syncthreads();
 }
 
+// Reflector entry as an operand when the heads lie in the block: zero above
+// the head row, one on it.
+template <typename C>
+__device__ __forceinline__ C vunit(C x, int r, int c) {
+    return (r > c) ? x : ((r == c) ? C(1) : C(0));
+}
+
+// ---------------------------------------------------------------- 64-row blocks
+// The chain kernel for 64-row blocks: four waves, wave w owning rows
+// 16w..16w+15 of each block and (for w < n/16) the slab tile w.  The next
+// block's reflectors, rows of B and T fragments are loaded into registers
+// while the current block is processed.  Per block:
+//   1. partial W_w = Y_w^T X_w on each wave (16 rows), to LDS;
+//   2. wave p sums the partials of tile p (+ its slab tile) -> W_p, to LDS;
+//   3. wave p: W'_p from T's blocks (loaded straight into the A-operand
+//      layout) and the W tiles; slab tile p -= W'_p; W'_p to LDS;
+//   4. every wave: X_w -= Y_w W' (Y_w transposed through its LDS tile).
+template <typename S, typename C, int NP>
+struct Apply64Smem {
+    C part[4][NP][4][64];  // per-wave partials; part[0] holds the sums
+    C wp[NP][4][64];       // W' tiles (MFMA D layout, lane-major)
+    C trans[4][16][17];    // per-wave transposes
+};
+
+template <typename S, typename C, int NP, int MODE>
+struct Apply64Regs {
+    C y[4][NP];  // Y rows 16w + orow(l4, i), columns 16p + l16
+    C x[4];      // B rows 16w + orow(l4, i), column col
+    C t[NP][4];  // T fragments of this wave's W' tile (A-operand layout)
+};
+
+template <typename S, typename C, int NP, int MODE>
+__device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int wv, int l16, int l4, int n,
+                                             const S* __restrict__ Y, int64_t ldy, const S* __restrict__ Tb,
+                                             const S* __restrict__ B, int64_t ldb, int64_t r0, int rows, bool top,
+                                             int64_t col, bool colok) {
+    typedef Mfma<C> M;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 16 * wv + M::orow(l4, i);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int cc = 16 * p + l16;
+            C v = (r < rows && cc < n) ? (C)Y[(r0 + r) * ldy + cc] : C(0);
+            if (top) v = (cc < n) ? vunit(v, r, cc) : C(0);
+            R.y[i][p] = v;
+        }
+        R.x[i] = (MODE != MODE_FORMQ && r < rows && colok) ? (C)B[(r0 + r) * ldb + col] : C(0);
+    }
+    // T fragments for output tile p = wv: QT uses (T_qp)^T (q <= p), Q uses T_pq (q >= p)
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            int ti, tj;
+            if (MODE == MODE_QT) {
+                ti = 16 * q + M::orow(l4, kc);
+                tj = 16 * wv + l16;
+            } else {
+                ti = 16 * wv + l16;
+                tj = 16 * q + M::orow(l4, kc);
+            }
+            const bool ok = wv < NP && ti <= tj && tj < n;
+            R.t[q][kc] = ok ? (C)Tb[(int64_t)tj * (tj + 1) / 2 + ti] : C(0);
+        }
+}
+
+template <typename S, typename C, int NP, int MODE>
+__device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64Regs<S, C, NP, MODE>& R,
+                                              C (&sl)[4], int wv, int l16, int l4, int n, S* __restrict__ B,
+                                              int64_t ldb, int64_t r0, int rows, bool top, int64_t col, bool colok) {
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    const int lane = threadIdx.x & 63;
+    // first block in the Q direction: its first n rows are the slab
+    if (MODE != MODE_QT && top && wv < NP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * wv + M::orow(l4, i);
+            if (r < n) R.x[i] = sl[i];
+        }
+    }
+    // Explicit Q, blocks past the first: the block's rows of B are zero, so
+    // W is the slab itself and steps 1-2 reduce to publishing the slab tiles.
+    if (MODE == MODE_FORMQ && !top) {
+        if (wv < NP) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.part[0][wv][r][lane] = sl[r];
+        }
+        __syncthreads();
+    } else {
+    // 1. partial W over this wave's rows
+    {
+        acc_t acc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[p] = acc_t{0, 0, 0, 0};
+        if (!(MODE == MODE_FORMQ && !top)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) acc[p] = M::mma(R.y[i][p], R.x[i], acc[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.part[wv][p][r][lane] = acc[p][r];
+    }
+    __syncthreads();
+    // 2. wave p: W_p = sum of partials (+ slab tile p)
+    if (wv < NP) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            C v = sm.part[0][wv][r][lane] + sm.part[1][wv][r][lane];
+            v += sm.part[2][wv][r][lane];
+            v += sm.part[3][wv][r][lane];
+            if (!top) v += sl[r];
+            sm.part[0][wv][r][lane] = v;
+        }
+    }
+    __syncthreads();
+    }
+    // 3. wave p: -W'_p, slab tile p
+    if (wv < NP) {
+        acc_t nw = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                if (MODE == MODE_QT ? (q > wv) : (q < wv)) continue;
+                nw = M::mma(-R.t[q][kc], sm.part[0][q][kc][lane], nw);
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sm.wp[wv][r][lane] = nw[r];
+            if (!top) sl[r] += nw[r];
+        }
+    }
+    __syncthreads();
+    // 4. X -= Y W'
+    {
+        acc_t u = acc_t{R.x[0], R.x[1], R.x[2], R.x[3]};
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sm.trans[wv][M::orow(l4, i)][l16] = R.y[i][p];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            C yt[4];
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) yt[kc] = sm.trans[wv][l16][M::orow(l4, kc)];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) u = M::mma(yt[kc], sm.wp[p][kc][lane], u);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * wv + M::orow(l4, i);
+            if (MODE == MODE_QT && top && wv < NP && r < n) sl[i] = u[i];
+            if (r < rows && colok) B[(r0 + r) * ldb + col] = (S)u[i];
+        }
+    }
+}
+
+template <typename S, typename C, int NP, int MODE>
+__global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __restrict__ Y, int64_t ldy,
+                                                          const S* __restrict__ T_blk, S* __restrict__ B,
+                                                          int64_t ldb, int64_t k, int ntiles) {
+    typedef Mfma<C> M;
+    __shared__ Apply64Smem<S, C, NP> sm;
+    const int gid = blockIdx.x;
+    const int x8 = gid & 7, yq = gid >> 3;
+    const int chain = (yq / ntiles) * 8 + x8;
+    const int tile = yq - (yq / ntiles) * ntiles;
+    if (chain >= g.W) return;
+    const int n = (int)g.n;
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)tile * 16 + l16;
+    const bool colok = col < k;
+    const int64_t start = chain_start(g, chain), end = chain_end(g, chain);
+    const int nb = chain_nblocks(g, chain);
+    const int64_t blk0 = chain_blk0(g, chain);
+    // slab tile wv (D layout = the natural rows 16wv + orow(l4, i) of the chain's first rows)
+    C sl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = 16 * wv + M::orow(l4, i);
+        sl[i] = (MODE != MODE_QT && wv < NP && j < n && colok) ? (C)B[(start + j) * ldb + col] : C(0);
+    }
+    Apply64Regs<S, C, NP, MODE> cur, nxt;
+    auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
+    auto load = [&](Apply64Regs<S, C, NP, MODE>& R, int bi) {
+        const int b = blk(bi);
+        const int64_t r0 = start + (int64_t)b * 64;
+        const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+        apply64_load<S, C, NP, MODE>(R, wv, l16, l4, n, Y, ldy, T_blk + (blk0 + b) * tri, B, ldb, r0, rows, b == 0,
+                                     col, colok);
+    };
+    auto run = [&](Apply64Regs<S, C, NP, MODE>& R, int bi) {
+        const int b = blk(bi);
+        const int64_t r0 = start + (int64_t)b * 64;
+        const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+        apply64_block<S, C, NP, MODE>(sm, R, sl, wv, l16, l4, n, B, ldb, r0, rows, b == 0, col, colok);
+    };
+    load(cur, 0);
+    for (int bi = 0; bi < nb; bi += 2) {
+        if (bi + 1 < nb) load(nxt, bi + 1);
+        run(cur, bi);
+        if (bi + 1 >= nb) break;
+        if (bi + 2 < nb) load(cur, bi + 2);
+        run(nxt, bi + 1);
+    }
+    if (MODE == MODE_QT && wv < NP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * wv + M::orow(l4, i);
+            if (j < n && colok) B[(start + j) * ldb + col] = (S)sl[i];
+        }
+    }
+}
+
 template <typename S, typename C, int NC, int H, int MODE>
 __global__ __launch_bounds__(256) void k_chain_apply(Geom g, const S* __restrict__ Y, int64_t ldy,
                                                      const S* __restrict__ T_blk, S* __restrict__ B, int64_t ldb,
@@ -259,8 +481,12 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     const int groups = (g.W + 7) / 8;
     const int64_t grid = (int64_t)groups * 8 * ntiles;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    constexpr int NP = NC <= 16 ? 1 : NC / 16;
     phase_begin(1 + MODE, st);
-    k_chain_apply<S, C, NC, H, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
+    if constexpr (H == 64)
+        k_chain_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
+    else
+        k_chain_apply<S, C, NC, H, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
     phase_end(1 + MODE, st);
     return hipGetLastError();
 }
@@ -282,12 +508,8 @@ static hipError_t node_apply_launch(const Geom& g, int lev, const Work& wk, S* B
 template <typename S, typename C, int NC, int MODE>
 static hipError_t chain_apply_h(const Geom& g, const S* Y, int64_t ldy, const Work& wk, S* B, int64_t ldb, int64_t k,
                                 hipStream_t st) {
-    switch (g.h) {
-        case 64: return chain_apply_launch<S, C, NC, 64, MODE>(g, Y, ldy, wk, B, ldb, k, st);
-        case 128: return chain_apply_launch<S, C, NC, 128, MODE>(g, Y, ldy, wk, B, ldb, k, st);
-        case 256: return chain_apply_launch<S, C, NC, 256, MODE>(g, Y, ldy, wk, B, ldb, k, st);
-        default: return hipErrorInvalidValue;
-    }
+    if (g.h != 64) return hipErrorInvalidValue;
+    return chain_apply_launch<S, C, NC, 64, MODE>(g, Y, ldy, wk, B, ldb, k, st);
 }
 
 template <typename S, typename C, int NC, int MODE>
