@@ -97,13 +97,21 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     return 0;
 }
 
+// Elements of one chain's published R: its packed upper triangle (rows of
+// length 16 * panels), or n * n if larger.
+static size_t rslot_elems(const Geom& g) {
+    const size_t ncp = g.NC <= 16 ? 16 : (size_t)g.NC;
+    const size_t rp = ncp * (ncp + 1) / 2, nn = (size_t)g.n * g.n;
+    return nn > rp ? nn : rp;
+}
+
 size_t work_bytes(const Geom& g, bool f64) {
     const size_t es = f64 ? 8 : 4;
     const size_t n = (size_t)g.n, tri = n * (n + 1) / 2;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t ncnt = (size_t)g.W * (g.levels > 0 ? g.levels : 1);
-    return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + 2 * al((size_t)g.W * n * n * es) +
-           al((size_t)g.W * tri * es) + al((size_t)g.W * n * es) + al(ncnt * 4);
+    return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + al((size_t)g.W * rslot_elems(g) * es) +
+           al((size_t)g.W * n * n * es) + al((size_t)g.W * tri * es) + al((size_t)g.W * n * es) + al(ncnt * 4);
 }
 
 void work_carve(Work* w, const Geom& g, bool f64) {
@@ -116,7 +124,7 @@ void work_carve(Work* w, const Geom& g, bool f64) {
     w->T_blk = p;
     p += al(g.nblocks * tri * es);
     w->Rbuf = p;
-    p += al((size_t)g.W * n * n * es);
+    p += al((size_t)g.W * rslot_elems(g) * es);
     w->Ynode = p;
     p += al((size_t)g.W * n * n * es);
     w->Tnode = p;

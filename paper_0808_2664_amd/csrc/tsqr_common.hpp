@@ -52,7 +52,7 @@ struct Work {
     size_t bytes = 0;
     void* tau_blk = nullptr;   // nblocks x n
     void* T_blk = nullptr;     // nblocks x n(n+1)/2, packed upper, column by column
-    void* Rbuf = nullptr;      // W x n x n
+    void* Rbuf = nullptr;      // W slots: each chain's packed R, published for the tree
     void* Ynode = nullptr;     // W x n x n  (slot c holds the step folding chain c)
     void* Tnode = nullptr;     // W x n(n+1)/2
     void* tau_node = nullptr;  // W x n

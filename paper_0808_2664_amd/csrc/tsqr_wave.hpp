@@ -174,8 +174,10 @@ __device__ __forceinline__ void hh_scalars(float alpha, float sigma2, float& bet
 template <typename T, int NP>
 struct WSmem {
     static constexpr int NCP = 16 * NP;
-    T R[NCP * (NCP + 1) / 2];  // on-chip R, upper triangle packed by rows
-    T scr[16][17];             // transposes and T staging
+    static constexpr int RP = NCP * (NCP + 1) / 2;
+    T R[RP];            // on-chip R, upper triangle packed by rows
+    T scr[16][17];      // transposes
+    T td[NP][16][17];   // diagonal T blocks of the panels (row l of block p in td[p][l])
 };
 // Packed index of R[r][c], c >= r, rows of length NCP.
 template <int NCP>
@@ -282,15 +284,15 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             sc_lane = (l16 == jj) ? scale : sc_lane;
             tau_lane = (l16 == jj) ? tau : tau_lane;
             // in-panel Gram P[c][j] = v_c^T v_j (lanes c < j) and column j of the
-            // panel's T (row l16 per lane group, kept in sm.scr):
+            // panel's T (row l16 per lane group, kept in sm.td[p]):
             // T[a][j] = -tau_j sum_{k<j} T[a][k] P[k][j], T[j][j] = tau_j
             const T pw = sc_lane * w;
             T t = T(0);
             sfor<0, jj>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                t = fma(sm.scr[l16][k], bcast16<k>(pw), t);
+                t = fma(sm.td[p][l16][k], bcast16<k>(pw), t);
             });
-            if (l4 == 0) sm.scr[l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
+            if (l4 == 0) sm.td[p][l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
         });
 
         // reflector tails: scale the panel's columns (delayed from the sweep)
@@ -310,7 +312,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
         wave_sync();
         T tpp[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tpp[r] = sm.scr[M::orow(l4, r)][l16];
+        for (int r = 0; r < 4; ++r) tpp[r] = sm.td[p][M::orow(l4, r)][l16];
         wave_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -460,17 +462,16 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             }
         });
         emit();
-        // diagonal blocks back from this wave's stores: D layout (tD) and
-        // A-operand layout (tA)
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        // diagonal blocks from LDS: D layout (tD) and A-operand layout (tA)
+        // (entries beyond n and below the diagonal are zero in td)
         T tD[NP][4], tA[NP][4];
         sfor<0, NP>([&](auto bc) {
             constexpr int b = decltype(bc)::value;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int o = M::orow(l4, r);
-                tD[b][r] = (o <= l16 && 16 * b + l16 < n) ? Tout[tpi(16 * b + o, 16 * b + l16)] : T(0);
-                tA[b][r] = (l16 <= o && 16 * b + o < n) ? Tout[tpi(16 * b + l16, 16 * b + o)] : T(0);
+                tD[b][r] = sm.td[b][o][l16];
+                tA[b][r] = sm.td[b][l16][o];
             }
         });
         // T_ab = -T_aa sum_{c=a+1..b} P_ac T_cb, a = b-1 .. 0
@@ -576,15 +577,52 @@ __device__ __forceinline__ void r_out(const WSmem<T, NP>& sm, int n, T* __restri
         if (j < n && (j >= i || lower)) R[i * ldr + j] = (j >= i) ? sm.R[rpi<NCP>(i, j >= i ? j : i)] : T(0);
     }
 }
-// Row-major R (upper part) -> LDS.
+// The packed R travels through global memory as is (slot of rslot(n, NP)
+// elements); copies are coalesced and independent.
+template <int NP>
+__host__ __device__ inline int64_t rslot(int64_t n) {
+    const int64_t rp = (int64_t)(16 * NP) * (16 * NP + 1) / 2;
+    return n * n > rp ? n * n : rp;
+}
 template <typename T, int NP>
-__device__ __forceinline__ void r_in(WSmem<T, NP>& sm, int n, const T* __restrict__ R) {
-    constexpr int NCP = 16 * NP;
-    const int j = lane_id();
-    for (int i = 0; i < n; ++i) {
-        if (j < n && j >= i) sm.R[rpi<NCP>(i, j)] = R[i * n + j];
-    }
+__device__ __forceinline__ void r_pub(const WSmem<T, NP>& sm, T* __restrict__ dst) {
+    constexpr int RP = WSmem<T, NP>::RP;
+    const int l = lane_id();
+#pragma unroll 4
+    for (int e = l; e < RP; e += 64) dst[e] = sm.R[e];
+}
+template <typename T, int NP>
+__device__ __forceinline__ void r_get(WSmem<T, NP>& sm, const T* __restrict__ src) {
+    constexpr int RP = WSmem<T, NP>::RP;
+    constexpr int IT = (RP + 63) / 64;
+    const int l = lane_id();
+    T v[IT];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) v[t] = (l + 64 * t < RP) ? src[l + 64 * t] : T(0);
+#pragma unroll
+    for (int t = 0; t < IT; ++t)
+        if (l + 64 * t < RP) sm.R[l + 64 * t] = v[t];
     wave_sync();
+}
+// Tile (operand layout) of a packed upper-triangular R (global or LDS).
+template <typename T, int NP>
+__device__ __forceinline__ void tile_of_packed(T (&x)[NP][4][NP], const T* __restrict__ Rp, int n) {
+    typedef Mfma<T> M;
+    constexpr int NCP = 16 * NP;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * s + M::orow(l4, i);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int cc = 16 * q + l16;
+                const bool ok = cc >= r && cc < n && r < n;
+                const T v = Rp[rpi<NCP>(ok ? r : 0, ok ? cc : 0)];
+                x[s][i][q] = ok ? v : T(0);
+            }
+        }
 }
 
 // ---- one chain, then the tree nodes this wave completes -----------------------------
@@ -633,6 +671,7 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         }
     }
     // ---- the tree
+    const int64_t rs = rslot<NP>(n);
     int cur = c;
     for (int lev = 1; lev <= g.levels; ++lev) {
         const int64_t stride = ipow(g.arity, lev - 1);
@@ -641,24 +680,41 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         int nch = (int)((g.W - i0 + stride - 1) / stride);
         if (nch > g.arity) nch = g.arity;
         if (nch <= 1) continue;  // unpaired: carried up unchanged
-        r_out<T, NP>(sm, n, Rbuf + (int64_t)cur * nn, n, true);
+        r_pub<T, NP>(sm, Rbuf + (int64_t)cur * rs);
         __threadfence();
         int old = 0;
         if ((threadIdx.x & 63) == 0) old = atomicAdd(ta.cnt + (int64_t)(lev - 1) * g.W + i0, 1);
         old = __builtin_amdgcn_readfirstlane(old);
         if (old != nch - 1) return;
         __threadfence();
-        if (cur != i0) r_in<T, NP>(sm, n, Rbuf + (int64_t)i0 * nn);
+        // The node folds children 1..nch-1 into child 0 in order, whichever
+        // child arrived last.  This wave's own R is taken from LDS, the others
+        // from their published copies.
+        T own[NP][4][NP];
+        const int tself = (int)((cur - i0) / stride);
+        if (tself != 0) {
+            tile_of_packed<T, NP>(own, sm.R, n);
+            wave_sync();
+            r_get<T, NP>(sm, Rbuf + (int64_t)i0 * rs);
+        }
         for (int t = 1; t < nch; ++t) {
             const int64_t ch = i0 + t * stride;
             T xc[NP][4][NP];
-            wload<T, NP, NP>(xc, Rbuf + ch * nn, n, 0, n, n);
+            if (t == tself) {
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int q = 0; q < NP; ++q) xc[a][i][q] = own[a][i][q];
+            } else {
+                tile_of_packed<T, NP>(xc, Rbuf + ch * rs, n);
+            }
             auto emit = [&]() { wstore<T, NP, NP>(xc, Ynode + ch * nn, n, 0, n, n); };
             wave_block<T, NP, NP, 2>(xc, sm, n, Tnode + ch * tri, tau_node + ch * n, emit);
         }
         cur = i0;
     }
-    r_out<T, NP>(sm, n, Rbuf, n, true);
     if (ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
 }
 
