@@ -15,159 +15,18 @@
 // and run on the MFMA units (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4);
 // FP32 compute with FP64 storage is the mixed-precision CAQR update.
 //
-// Workgroup = 4 waves, each owning H/4 rows of the block; 16 columns of B per
-// workgroup.  Workgroups are numbered so that all column tiles of one chain
-// land on the same XCD (dispatch is round robin over the 8 XCDs), so the
+// Workgroup = 4 waves, each owning 16 rows of a 64-row block; 16 columns of B
+// per workgroup.  Workgroups are numbered so that all column tiles of one
+// chain land on the same XCD (dispatch is round robin over the 8 XCDs), so the
 // block's reflectors are fetched from HBM once and re-read from that XCD's L2.
+// Q^T runs the chains in one launch and every tree level in a second one;
+// Q and the explicit Q run the tree levels top-down, one launch per level,
+// then the chains.
 #include "tsqr_common.hpp"
 
 namespace tsqr {
 using namespace dev;
 
-template <typename S, typename C, int NC>
-struct ApplySmem {
-    static constexpr int NCP = NC < 16 ? 16 : NC;
-    union U {
-        C Wpart[4][NCP][16];
-        C trans[4][16][17];
-    } u;
-    C Wp[NCP][17];
-    S slab[NCP][16];
-    C Tl[NCP * (NCP + 1) / 2 + 16];
-};
-
-// One block reflector applied to a (rows x 16) column tile.
-//   Yg/ldy/yrow0: reflector rows of the block; Bg/ldb/brow0: the tile rows;
-//   top: chain block 0 (unit lower trapezoid, no separate slab);
-//   MODE_QT uses T^T, MODE_Q / MODE_FORMQ use T.  MODE_FORMQ treats the
-//   input rows as zero (explicit Q of [I; 0]).
-template <typename S, typename C, int NC, int H, int MODE>
-__device__ __forceinline__ void apply_block(ApplySmem<S, C, NC>& sm, int n, const S* __restrict__ Yg, int64_t ldy,
-                                            int64_t yrow0, S* __restrict__ Bg, int64_t ldb, int64_t brow0, int rows,
-                                            int64_t col0, int64_t k, bool top, const S* __restrict__ Tpk) {
-    typedef Mfma<C> M;
-    typedef typename M::acc acc_t;
-    constexpr int NCP = ApplySmem<S, C, NC>::NCP;
-    constexpr int NP = NCP / 16;
-    constexpr int RW = H / 4;
-    constexpr int SG = RW / 16;
-    static_assert(SG >= 1, "block height too small");
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int l16 = lane & 15, l4 = lane >> 4;
-    const int tri = n * (n + 1) / 2;
-
-    for (int e = tid; e < tri; e += 256) sm.Tl[e] = (C)Tpk[e];
-
-    C ynat[SG][4][NP];
-    S bt[SG][4];
-#pragma unroll
-    for (int s = 0; s < SG; ++s) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = wv * RW + 16 * s + M::orow(l4, i);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int cc = 16 * p + l16;
-                C yv = C(0);
-                if (r < rows && cc < n) yv = (C)Yg[(yrow0 + r) * ldy + cc];
-                if (top && r < n) yv = (cc < r) ? yv : (cc == r ? C(1) : C(0));
-                ynat[s][i][p] = yv;
-            }
-            const int64_t col = col0 + l16;
-            S b = S(0);
-            if (MODE != MODE_QT && top && r < n) b = sm.slab[r][l16];
-            else if (MODE != MODE_FORMQ && r < rows && col < k) b = Bg[(brow0 + r) * ldb + col];
-            bt[s][i] = b;
-        }
-    }
-
-    // W partial = Y^T X over this wave's rows
-    acc_t acc[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) acc[p] = acc_t{0, 0, 0, 0};
-    if (!(MODE == MODE_FORMQ && !top)) {
-#pragma unroll
-        for (int s = 0; s < SG; ++s)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const C bv = (C)bt[s][i];
-#pragma unroll
-                for (int p = 0; p < NP; ++p) acc[p] = M::mma(ynat[s][i][p], bv, acc[p]);
-            }
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sm.u.Wpart[wv][16 * p + M::orow(l4, r)][l16] = acc[p][r];
-    __syncthreads();
-    for (int e = tid; e < NCP * 16; e += 256) {
-        const int j = e >> 4, cc = e & 15;
-        C sum = sm.u.Wpart[0][j][cc] + sm.u.Wpart[1][j][cc];
-        sum += sm.u.Wpart[2][j][cc];
-        sum += sm.u.Wpart[3][j][cc];
-        if (!top && j < n) sum += (C)sm.slab[j][cc];
-        sm.u.Wpart[0][j][cc] = sum;
-    }
-    __syncthreads();
-    // W' = T^T W (Q^T) or T W (Q); T upper triangular, packed by columns
-    if (wv < NP) {
-        acc_t a2 = acc_t{0, 0, 0, 0};
-        const int m = 16 * wv + l16;
-        const int qlo = (MODE == MODE_QT) ? 0 : 4 * wv;
-        const int qhi = (MODE == MODE_QT) ? 4 * wv + 4 : NCP / 4;
-        for (int q = qlo; q < qhi; ++q) {
-            const int kk = 4 * q + l4;
-            const int ti = (MODE == MODE_QT) ? kk : m;
-            const int tj = (MODE == MODE_QT) ? m : kk;
-            const C a = (ti <= tj && tj < n) ? sm.Tl[tj * (tj + 1) / 2 + ti] : C(0);
-            a2 = M::mma(a, sm.u.Wpart[0][kk][l16], a2);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sm.Wp[16 * wv + M::orow(l4, r)][l16] = a2[r];
-    }
-    __syncthreads();
-    if (!top) {
-        for (int e = tid; e < n * 16; e += 256) {
-            const int j = e >> 4, cc = e & 15;
-            sm.slab[j][cc] -= (S)sm.Wp[j][cc];
-        }
-    }
-    // X -= Y W'
-#pragma unroll
-    for (int s = 0; s < SG; ++s) {
-        acc_t u = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sm.u.trans[wv][M::orow(l4, i)][l16] = ynat[s][i][p];
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const C a = sm.u.trans[wv][l16][4 * q + l4];
-                const C bb = sm.Wp[16 * p + 4 * q + l4][l16];
-                u = M::mma(a, bb, u);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bt[s][i] -= (S)u[i];
-    }
-#pragma unroll
-    for (int s = 0; s < SG; ++s)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = wv * RW + 16 * s + M::orow(l4, i);
-            const int64_t col = col0 + l16;
-            if (r < rows && col < k) Bg[(brow0 + r) * ldb + col] = bt[s][i];
-            if (MODE == MODE_QT && top && r < n) sm.slab[r][l16] = bt[s][i];
-        }
-    __syncthreads();
-}
-
-// Reflector entry as an operand when the heads lie in the block: zero above
-// the head row, one on it.
 template <typename C>
 __device__ __forceinline__ C vunit(C x, int r, int c) {
     return (r > c) ? x : ((r == c) ? C(1) : C(0));
@@ -197,7 +56,8 @@ struct Apply64Regs {
     C t[NP][4];  // T fragments of this wave's W' tile (A-operand layout)
 };
 
-template <typename S, typename C, int NP, int MODE>
+// PUB: the rows of B were published by another workgroup of this launch.
+template <typename S, typename C, int NP, int MODE, bool PUB = false>
 __device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int wv, int l16, int l4, int n,
                                              const S* __restrict__ Y, int64_t ldy, const S* __restrict__ Tb,
                                              const S* __restrict__ B, int64_t ldb, int64_t r0, int rows, bool top,
@@ -213,7 +73,8 @@ __device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int
             if (top) v = (cc < n) ? vunit(v, r, cc) : C(0);
             R.y[i][p] = v;
         }
-        R.x[i] = (MODE != MODE_FORMQ && r < rows && colok) ? (C)B[(r0 + r) * ldb + col] : C(0);
+        const S* bp = B + (r0 + r) * ldb + col;
+        R.x[i] = (MODE != MODE_FORMQ && r < rows && colok) ? (C)(PUB ? pub_load(bp) : *bp) : C(0);
     }
     // T fragments for output tile p = wv: QT uses (T_qp)^T (q <= p), Q uses T_pq (q >= p)
 #pragma unroll
@@ -330,6 +191,70 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
     }
 }
 
+// Tree levels of Q^T in one launch (Sec. 2.1: the nodes of the tree of Q
+// factors are applied bottom-up).  Workgroup (node, tile) applies level-1
+// node `node` to one 16-column tile of B: child 0's slab (its chain's top n
+// rows of B) and each further child's slab are combined with that child's
+// node reflectors.  Then, level by level, the last of a node's children to
+// arrive (an arrival count per node and tile, zero at launch) applies the
+// node; the others leave.  Slabs pass between workgroups with
+// device-coherent stores and loads.
+template <typename S, typename C, int NP>
+__global__ __launch_bounds__(256, 2) void k_qt_tree64(Geom g, int ntiles, S* __restrict__ B, int64_t ldb, int64_t k,
+                                                      const S* __restrict__ Ynode, const S* __restrict__ Tnode,
+                                                      int* __restrict__ cnt) {
+    typedef Mfma<C> M;
+    __shared__ Apply64Smem<S, C, NP> sm;
+    __shared__ int s_old;
+    const int node = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - node * ntiles;
+    const int n = (int)g.n;
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)tile * 16 + l16;
+    const bool colok = col < k;
+    int cur = node * g.arity;
+    if (cur >= g.W) return;
+    for (int lev = 1; lev <= g.levels; ++lev) {
+        const int64_t stride = ipow(g.arity, lev - 1);
+        const int64_t span = stride * g.arity;
+        const int i0 = (int)((cur / span) * span);
+        int nch = (int)((g.W - i0 + stride - 1) / stride);
+        if (nch > g.arity) nch = g.arity;
+        if (nch <= 1) continue;  // unpaired: carried up unchanged
+        if (lev > 1) {
+            pub_wait();  // this workgroup's slab stores have landed
+            __syncthreads();
+            if (tid == 0) s_old = atomicAdd(cnt + (((int64_t)(lev - 2) * g.W + i0) * ntiles + tile), 1);
+            __syncthreads();
+            if (s_old != nch - 1) return;
+        }
+        const int64_t sa = chain_start(g, i0);
+        C sl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * wv + M::orow(l4, i);
+            sl[i] = (wv < NP && j < n && colok) ? (C)pub_load(B + (sa + j) * ldb + col) : C(0);
+        }
+        for (int t = 1; t < nch; ++t) {
+            const int64_t ch = i0 + t * stride;
+            S* Bc = B + chain_start(g, (int)ch) * ldb;
+            Apply64Regs<S, C, NP, MODE_QT> R;
+            apply64_load<S, C, NP, MODE_QT, true>(R, wv, l16, l4, n, Ynode + ch * n * n, n, Tnode + ch * tri, Bc,
+                                                  ldb, 0, n, false, col, colok);
+            apply64_block<S, C, NP, MODE_QT>(sm, R, sl, wv, l16, l4, n, Bc, ldb, 0, n, false, col, colok);
+        }
+        if (wv < NP) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 16 * wv + M::orow(l4, i);
+                if (j < n && colok) pub_store(B + (sa + j) * ldb + col, (S)sl[i]);
+            }
+        }
+        cur = i0;
+    }
+}
+
 template <typename S, typename C, int NP, int MODE>
 __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __restrict__ Y, int64_t ldy,
                                                           const S* __restrict__ T_blk, S* __restrict__ B,
@@ -388,82 +313,9 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
     }
 }
 
-template <typename S, typename C, int NC, int H, int MODE>
-__global__ __launch_bounds__(256) void k_chain_apply(Geom g, const S* __restrict__ Y, int64_t ldy,
-                                                     const S* __restrict__ T_blk, S* __restrict__ B, int64_t ldb,
-                                                     int64_t k, int ntiles) {
-    __shared__ ApplySmem<S, C, NC> sm;
-    const int gid = blockIdx.x;
-    const int x8 = gid & 7, y = gid >> 3;
-    const int chain = (y / ntiles) * 8 + x8;
-    const int tile = y - (y / ntiles) * ntiles;
-    if (chain >= g.W) return;
-    const int n = (int)g.n;
-    const int tri = n * (n + 1) / 2;
-    const int64_t col0 = (int64_t)tile * 16;
-    const int64_t start = chain_start(g, chain), end = chain_end(g, chain);
-    const int nb = chain_nblocks(g, chain);
-    const int64_t blk0 = chain_blk0(g, chain);
-    const int tid = threadIdx.x;
-    if (MODE != MODE_QT) {
-        for (int e = tid; e < n * 16; e += 256) {
-            const int j = e >> 4, cc = e & 15;
-            const int64_t col = col0 + cc;
-            sm.slab[j][cc] = (col < k) ? B[(start + j) * ldb + col] : S(0);
-        }
-        __syncthreads();
-    }
-    for (int bi = 0; bi < nb; ++bi) {
-        const int b = (MODE == MODE_QT) ? bi : nb - 1 - bi;
-        const int64_t r0 = start + (int64_t)b * H;
-        const int rows = (int)((end - r0) < H ? (end - r0) : H);
-        apply_block<S, C, NC, H, MODE>(sm, n, Y, ldy, r0, B, ldb, r0, rows, col0, k, b == 0,
-                                       T_blk + (blk0 + b) * tri);
-    }
-    if (MODE == MODE_QT) {
-        for (int e = tid; e < n * 16; e += 256) {
-            const int j = e >> 4, cc = e & 15;
-            const int64_t col = col0 + cc;
-            if (col < k) B[(start + j) * ldb + col] = sm.slab[j][cc];
-        }
-    }
-}
-
-template <typename S, typename C, int NC, int MODE>
-__global__ __launch_bounds__(256) void k_node_apply(Geom g, int lev, const S* __restrict__ Ynode,
-                                                    const S* __restrict__ Tnode, S* __restrict__ B, int64_t ldb,
-                                                    int64_t k, int ntiles) {
-    __shared__ ApplySmem<S, C, NC> sm;
-    const int node = blockIdx.x / ntiles;
-    const int tile = blockIdx.x - node * ntiles;
-    const int64_t stride = ipow(g.arity, lev - 1);
-    const int64_t i0 = (int64_t)node * g.arity * stride;
-    if (i0 + stride >= g.W) return;
-    const int n = (int)g.n;
-    const int tri = n * (n + 1) / 2;
-    const int64_t col0 = (int64_t)tile * 16;
-    const int tid = threadIdx.x;
-    const int64_t sa = chain_start(g, (int)i0);
-    for (int e = tid; e < n * 16; e += 256) {
-        const int j = e >> 4, cc = e & 15;
-        const int64_t col = col0 + cc;
-        sm.slab[j][cc] = (col < k) ? B[(sa + j) * ldb + col] : S(0);
-    }
-    __syncthreads();
-    int nch = 0;
-    for (int t1 = 1; t1 < g.arity && i0 + (int64_t)t1 * stride < g.W; ++t1) nch = t1;
-    for (int ti = 0; ti < nch; ++ti) {
-        const int t1 = (MODE == MODE_QT) ? ti + 1 : nch - ti;
-        const int64_t c = i0 + (int64_t)t1 * stride;
-        const int64_t sc = chain_start(g, (int)c);
-        apply_block<S, C, NC, 64, MODE>(sm, n, Ynode + c * n * n, n, 0, B, ldb, sc, n, col0, k, false,
-                                        Tnode + c * tri);
-    }
-    for (int e = tid; e < n * 16; e += 256) {
-        const int j = e >> 4, cc = e & 15;
-        const int64_t col = col0 + cc;
-        if (col < k) B[(sa + j) * ldb + col] = sm.slab[j][cc];
-    }
+__global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0;
 }
 
 template <typename T>
@@ -483,12 +335,76 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
     phase_begin(1 + MODE, st);
-    if constexpr (H == 64)
-        k_chain_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
-    else
-        k_chain_apply<S, C, NC, H, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
+    static_assert(H == 64, "the chain kernel takes 64-row blocks");
+    k_chain_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
     phase_end(1 + MODE, st);
     return hipGetLastError();
+}
+
+// All tree levels of Q^T in one launch; arrival counts (levels above the
+// first) live in a stream-ordered allocation cleared by a fill kernel.
+template <typename S, typename C, int NC>
+static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ldb, int64_t k, hipStream_t st) {
+    if (g.levels == 0) return hipSuccess;
+    constexpr int NP = NC <= 16 ? 1 : NC / 16;
+    const int ntiles = (int)((k + 15) / 16);
+    const int64_t nodes = (g.W + g.arity - 1) / g.arity;
+    int* cnt = nullptr;
+    const int64_t ncnt = (int64_t)g.W * (g.levels > 1 ? g.levels - 1 : 1) * ntiles;
+    hipError_t e = hipMallocAsync((void**)&cnt, (size_t)ncnt * sizeof(int), st);
+    if (e != hipSuccess) return e;
+    k_apply_zero<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(cnt, ncnt);
+    k_qt_tree64<S, C, NP><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
+                                                                       (const S*)wk.Tnode, cnt);
+    e = hipGetLastError();
+    hipError_t e2 = hipFreeAsync(cnt, st);
+    return e != hipSuccess ? e : e2;
+}
+
+// One tree level of Q (explicit Q or Q*B; Sec. 2.1, the tree of Q factors
+// applied top-down): workgroup (node, tile) applies the node's steps, last
+// child first, to [slab of child 0; slab of child t] for one 16-column tile.
+// For the explicit Q the slabs of children t >= 1 are still zero here.
+template <typename S, typename C, int NP, int MODE>
+__global__ __launch_bounds__(256, 2) void k_node_apply64(Geom g, int lev, int ntiles, S* __restrict__ B,
+                                                         int64_t ldb, int64_t k, const S* __restrict__ Ynode,
+                                                         const S* __restrict__ Tnode) {
+    typedef Mfma<C> M;
+    __shared__ Apply64Smem<S, C, NP> sm;
+    const int node = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - node * ntiles;
+    const int n = (int)g.n;
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)tile * 16 + l16;
+    const bool colok = col < k;
+    const int64_t stride = ipow(g.arity, lev - 1);
+    const int64_t i0 = (int64_t)node * g.arity * stride;
+    int nch = (int)((g.W - i0 + stride - 1) / stride);
+    if (nch > g.arity) nch = g.arity;
+    if (nch <= 1) return;
+    const int64_t sa = chain_start(g, (int)i0);
+    C sl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = 16 * wv + M::orow(l4, i);
+        sl[i] = (wv < NP && j < n && colok) ? (C)B[(sa + j) * ldb + col] : C(0);
+    }
+    for (int t = nch - 1; t >= 1; --t) {
+        const int64_t ch = i0 + t * stride;
+        S* Bc = B + chain_start(g, (int)ch) * ldb;
+        Apply64Regs<S, C, NP, MODE> R;
+        apply64_load<S, C, NP, MODE>(R, wv, l16, l4, n, Ynode + ch * n * n, n, Tnode + ch * tri, Bc, ldb, 0, n, false,
+                                     col, colok);
+        apply64_block<S, C, NP, MODE>(sm, R, sl, wv, l16, l4, n, Bc, ldb, 0, n, false, col, colok);
+    }
+    if (wv < NP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * wv + M::orow(l4, i);
+            if (j < n && colok) B[(sa + j) * ldb + col] = (S)sl[i];
+        }
+    }
 }
 
 template <typename S, typename C, int NC, int MODE>
@@ -500,8 +416,9 @@ static hipError_t node_apply_launch(const Geom& g, int lev, const Work& wk, S* B
     const int64_t nodes = (g.W + span - 1) / span;
     const int64_t grid = nodes * ntiles;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    k_node_apply<S, C, NC, MODE><<<(int)grid, 256, 0, st>>>(g, lev, (const S*)wk.Ynode, (const S*)wk.Tnode, B, ldb,
-                                                            k, ntiles);
+    constexpr int NP = NC <= 16 ? 1 : NC / 16;
+    k_node_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, lev, ntiles, B, ldb, k, (const S*)wk.Ynode,
+                                                              (const S*)wk.Tnode);
     return hipGetLastError();
 }
 
@@ -518,8 +435,7 @@ static hipError_t apply_mode(const Geom& g, const S* Y, int64_t ldy, const Work&
     hipError_t e = hipSuccess;
     if (MODE == MODE_QT) {
         e = chain_apply_h<S, C, NC, MODE>(g, Y, ldy, wk, B, ldb, k, st);
-        for (int lev = 1; lev <= g.levels && e == hipSuccess; ++lev)
-            e = node_apply_launch<S, C, NC, MODE>(g, lev, wk, B, ldb, k, st);
+        if (e == hipSuccess) e = qt_tree_launch<S, C, NC>(g, wk, B, ldb, k, st);
     } else {
         for (int lev = g.levels; lev >= 1 && e == hipSuccess; --lev)
             e = node_apply_launch<S, C, NC, MODE>(g, lev, wk, B, ldb, k, st);

@@ -191,5 +191,34 @@ struct Mfma<float> {
     __host__ __device__ static constexpr int row_l4(int rho) { return rho >> 2; }
 };
 
+// ---- hand-over between workgroups of one launch ----
+// The L2 caches of the chip's XCDs are not coherent with one another for
+// ordinary stores, so a device-scope fence has to write a whole L2 back to
+// memory; with many workgroups fencing while others stream output, those
+// write-backs serialise.  Data handed from one workgroup to another inside a
+// launch (a published R factor or slab) therefore uses device-coherent
+// accesses instead: written through to memory (pub_store), awaited before the
+// arrival is counted (pub_wait), and read past any non-coherent cached copy
+// (pub_load).  No other memory needs to be visible at that point.
+template <typename T>
+struct PubBits;
+template <>
+struct PubBits<double> { typedef unsigned long long U; };
+template <>
+struct PubBits<float> { typedef unsigned int U; };
+
+template <typename T>
+__device__ __forceinline__ void pub_store(T* p, T v) {
+    typedef typename PubBits<T>::U U;
+    __hip_atomic_store((U*)p, __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T pub_load(const T* p) {
+    typedef typename PubBits<T>::U U;
+    return __builtin_bit_cast(T, __hip_atomic_load((U*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// every vector memory access of this wave has completed (stores acknowledged)
+__device__ __forceinline__ void pub_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 }  // namespace dev
 }  // namespace tsqr

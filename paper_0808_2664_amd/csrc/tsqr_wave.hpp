@@ -589,7 +589,7 @@ __device__ __forceinline__ void r_pub(const WSmem<T, NP>& sm, T* __restrict__ ds
     constexpr int RP = WSmem<T, NP>::RP;
     const int l = lane_id();
 #pragma unroll 4
-    for (int e = l; e < RP; e += 64) dst[e] = sm.R[e];
+    for (int e = l; e < RP; e += 64) pub_store(dst + e, sm.R[e]);
 }
 template <typename T, int NP>
 __device__ __forceinline__ void r_get(WSmem<T, NP>& sm, const T* __restrict__ src) {
@@ -598,14 +598,15 @@ __device__ __forceinline__ void r_get(WSmem<T, NP>& sm, const T* __restrict__ sr
     const int l = lane_id();
     T v[IT];
 #pragma unroll
-    for (int t = 0; t < IT; ++t) v[t] = (l + 64 * t < RP) ? src[l + 64 * t] : T(0);
+    for (int t = 0; t < IT; ++t) v[t] = (l + 64 * t < RP) ? pub_load(src + l + 64 * t) : T(0);
 #pragma unroll
     for (int t = 0; t < IT; ++t)
         if (l + 64 * t < RP) sm.R[l + 64 * t] = v[t];
     wave_sync();
 }
-// Tile (operand layout) of a packed upper-triangular R (global or LDS).
-template <typename T, int NP>
+// Tile (operand layout) of a packed upper-triangular R, from LDS or (PUB) from
+// a copy published by another workgroup.
+template <typename T, int NP, bool PUB = false>
 __device__ __forceinline__ void tile_of_packed(T (&x)[NP][4][NP], const T* __restrict__ Rp, int n) {
     typedef Mfma<T> M;
     constexpr int NCP = 16 * NP;
@@ -619,7 +620,8 @@ __device__ __forceinline__ void tile_of_packed(T (&x)[NP][4][NP], const T* __res
             for (int q = 0; q < NP; ++q) {
                 const int cc = 16 * q + l16;
                 const bool ok = cc >= r && cc < n && r < n;
-                const T v = Rp[rpi<NCP>(ok ? r : 0, ok ? cc : 0)];
+                const T* a = Rp + rpi<NCP>(ok ? r : 0, ok ? cc : 0);
+                const T v = PUB ? pub_load(a) : *a;
                 x[s][i][q] = ok ? v : T(0);
             }
         }
@@ -681,12 +683,11 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         if (nch > g.arity) nch = g.arity;
         if (nch <= 1) continue;  // unpaired: carried up unchanged
         r_pub<T, NP>(sm, Rbuf + (int64_t)cur * rs);
-        __threadfence();
+        pub_wait();
         int old = 0;
         if ((threadIdx.x & 63) == 0) old = atomicAdd(ta.cnt + (int64_t)(lev - 1) * g.W + i0, 1);
         old = __builtin_amdgcn_readfirstlane(old);
         if (old != nch - 1) return;
-        __threadfence();
         // The node folds children 1..nch-1 into child 0 in order, whichever
         // child arrived last.  This wave's own R is taken from LDS, the others
         // from their published copies.
@@ -708,7 +709,7 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
 #pragma unroll
                         for (int q = 0; q < NP; ++q) xc[a][i][q] = own[a][i][q];
             } else {
-                tile_of_packed<T, NP>(xc, Rbuf + ch * rs, n);
+                tile_of_packed<T, NP, true>(xc, Rbuf + ch * rs, n);
             }
             auto emit = [&]() { wstore<T, NP, NP>(xc, Ynode + ch * nn, n, 0, n, n); };
             wave_block<T, NP, NP, 2>(xc, sm, n, Tnode + ch * tri, tau_node + ch * n, emit);
