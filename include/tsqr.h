@@ -66,7 +66,15 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                min(number of blocks, 1024).  chains = number of blocks
  *                gives the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
  *   arity      : fan-in of the tree over the chain R factors (default 2).
- *   flags      : reserved, must be 0. */
+ *   flags      : 0 or TSQR_FLAG_TREE_LEVELWISE.  By default a binary tree
+ *                whose chains all fit on the device at once is reduced
+ *                panel by panel (a node starts on its first 16 columns as
+ *                soon as its children have finished theirs); with this flag,
+ *                or when the tree is not binary or the chains do not fit,
+ *                each node starts when its children are complete.  Both give
+ *                the same bits; only the schedule differs (Sec. 2.1: the
+ *                tree shape and order are free). */
+#define TSQR_FLAG_TREE_LEVELWISE 1
 typedef struct tsqr_opts {
     int32_t block_rows;
     int32_t chains;

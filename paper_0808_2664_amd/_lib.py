@@ -20,6 +20,7 @@ TSQR_ERR_NOMEM = 2
 TSQR_ERR_PLAN = 3
 TSQR_ERR_UNSUPPORTED = 4
 TSQR_MAX_N = 64
+TSQR_FLAG_TREE_LEVELWISE = 1
 
 
 class TsqrOpts(ctypes.Structure):

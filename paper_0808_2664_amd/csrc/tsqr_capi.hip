@@ -66,7 +66,8 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     int h = (o && o->block_rows) ? o->block_rows : env_int("TSQR_BLOCK_ROWS", wave_default_h(NC));
     int chains = (o && o->chains) ? o->chains : env_int("TSQR_CHAINS", 0);
     int arity = (o && o->arity) ? o->arity : env_int("TSQR_ARITY", 2);
-    if (o && o->flags != 0) return TSQR_ERR_UNSUPPORTED;
+    const int flags = o ? o->flags : 0;
+    if (flags & ~TSQR_FLAG_TREE_LEVELWISE) return TSQR_ERR_UNSUPPORTED;
     if (!wave_shape_ok(NC, h)) return TSQR_ERR_UNSUPPORTED;
     if (arity < 2 || chains < 0) return TSQR_ERR_UNSUPPORTED;
     const int64_t blocks_total = (m + h - 1) / h;
@@ -94,6 +95,7 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     const int64_t last = m - (W - 1) * S;
     g->nblocks = (W - 1) * (S / h) + (last + h - 1) / h;
     g->NC = padded_nc(n);
+    g->flags = (flags & TSQR_FLAG_TREE_LEVELWISE) ? TREE_LEVELWISE : 0;
     return 0;
 }
 
@@ -109,7 +111,7 @@ size_t work_bytes(const Geom& g, bool f64) {
     const size_t es = f64 ? 8 : 4;
     const size_t n = (size_t)g.n, tri = n * (n + 1) / 2;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t ncnt = (size_t)g.W * (g.levels > 0 ? g.levels : 1);
+    const size_t ncnt = (size_t)g.W * (g.levels + 1);
     return al(g.nblocks * n * es) + al(g.nblocks * tri * es) + al((size_t)g.W * rslot_elems(g) * es) +
            al((size_t)g.W * n * n * es) + al((size_t)g.W * tri * es) + al((size_t)g.W * n * es) + al(ncnt * 4);
 }
@@ -194,7 +196,7 @@ int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, 
     if (!A) return -4;
     if (lda < n) return -5;
     if (R && ldr < n) return -7;
-    if (opts && (opts->flags != 0)) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
     if (!R && !q_out) return -9;
     tsqr_qtree_s* q = nullptr;
     int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream);
@@ -271,7 +273,7 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     if (panel < 1 || panel > TSQR_MAX_N) return -6;
     if (!check_dtype(update_dtype)) return -7;
     if (update_dtype == TSQR_F64 && dtype == TSQR_F32) return -7;
-    if (opts && opts->flags != 0) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = dtype == TSQR_F64;
     const bool cf64 = update_dtype == TSQR_F64;

@@ -23,7 +23,12 @@ struct Geom {
     int levels = 0;       // tree levels above the chains
     int64_t nblocks = 0;  // blocks over all chains
     int NC = 0;           // padded column count: 8, 16, 32 or 64
+    int flags = 0;        // TREE_LEVELWISE
 };
+
+// Geom::flags: reduce the tree node by node as children complete, never with
+// the panel-pipelined tree (the tsqr_opts flag of the same meaning).
+constexpr int TREE_LEVELWISE = 1;
 
 __host__ __device__ inline int64_t chain_start(const Geom& g, int c) { return (int64_t)c * g.S; }
 __host__ __device__ inline int64_t chain_end(const Geom& g, int c) {

@@ -16,13 +16,15 @@
 
 namespace tsqr {
 
-template <typename T, int NP, int SG>
+// PIPE: the panel-pipelined binary tree; launched cooperatively, so that
+// every wave is resident and a node's wave may wait for its children.
+template <typename T, int NP, int SG, bool PIPE>
 __global__ __launch_bounds__(64, TSQR_WAVE_OCC) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
                                                      T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                                      T* __restrict__ Ynode, T* __restrict__ Tnode,
                                                      T* __restrict__ tau_node, TreeArgs ta) {
     __shared__ WSmem<T, NP> sm;
-    wave_tsqr<T, NP, SG>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
+    wave_tsqr<T, NP, SG, PIPE>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
 }
 
 __global__ void k_zero_i32(int* __restrict__ p, int64_t count) {
@@ -53,10 +55,42 @@ int wave_default_h(int NC) {
     return 64;
 }
 
+// Workgroups of k_wave_tsqr<T, NP, SG, true> the device keeps resident at once.
+template <typename T, int NP, int SG>
+static int64_t pipe_capacity() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static int64_t cap[64];
+    static bool done[64];
+    if (dev < 0 || dev >= 64) return 0;
+    if (!done[dev]) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true>, 64, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = 0;
+        }
+        cap[dev] = (int64_t)per_cu * cus;
+        done[dev] = true;
+    }
+    return cap[dev];
+}
+
 template <typename T, int NP, int SG>
 static hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
-    k_wave_tsqr<T, NP, SG><<<g.W, 64, 0, st>>>(g, A, lda, (T*)wk.tau_blk, (T*)wk.T_blk, (T*)wk.Rbuf, (T*)wk.Ynode,
-                                               (T*)wk.Tnode, (T*)wk.tau_node, ta);
+    T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
+    T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
+    const bool pipe = g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG>();
+    if (pipe) {
+        Geom gg = g;
+        TreeArgs tt = ta;
+        void* args[] = {&gg, &A, &lda, &tau_blk, &T_blk, &Rbuf, &Ynode, &Tnode, &tau_node, &tt};
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true>, dim3(g.W), dim3(64),
+                                                  args, 0, st);
+        if (e == hipSuccess) return hipSuccess;
+        (void)hipGetLastError();  // not co-resident after all: reduce level by level
+    }
+    k_wave_tsqr<T, NP, SG, false><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
     return hipGetLastError();
 }
 
@@ -75,7 +109,7 @@ static hipError_t factor_t(const Geom& g, T* A, int64_t lda, const Work& wk, con
 
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
                          bool zero_lower, hipStream_t st) {
-    const int64_t ncnt = (int64_t)g.W * (g.levels > 0 ? g.levels : 1);
+    const int64_t ncnt = (int64_t)g.W * (g.levels + 1);
     k_zero_i32<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(wk.cnt, ncnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -181,7 +181,7 @@ struct WSmem {
 };
 // Packed index of R[r][c], c >= r, rows of length NCP.
 template <int NCP>
-__device__ __forceinline__ int rpi(int r, int c) {
+__host__ __device__ constexpr int rpi(int r, int c) {
     return r * NCP - ((r * (r - 1)) >> 1) + (c - r);
 }
 
@@ -200,9 +200,17 @@ __device__ __forceinline__ int64_t tpi(int i, int j) { return (int64_t)j * (j + 
 // After the panels, emit() is called while the tile still holds the final
 // reflectors (it stores them); the off-diagonal blocks of T follow from
 // registers, so the tile's registers are free again by then.
-template <typename T, int NP, int SG, int MODE, typename Emit>
+struct NoHook {
+    template <typename P>
+    __device__ void operator()(P) const {}
+};
+
+// pre(p) runs before panel p and post(p) once panel p's rows of R are final
+// (its sweep and its update of the trailing columns are done).
+template <typename T, int NP, int SG, int MODE, typename Emit, typename Pre = NoHook, typename Post = NoHook>
 __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, const int n_, T* __restrict__ Tout,
-                                           T* __restrict__ tauout, Emit&& emit) {
+                                           T* __restrict__ tauout, Emit&& emit, Pre&& pre = Pre{},
+                                           Post&& post = Post{}) {
     typedef Mfma<T> M;
     typedef typename M::acc acc_t;
     constexpr int NCP = 16 * NP;
@@ -212,6 +220,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
         constexpr int c0 = 16 * p;
         const int n = opaque_s(n_);
         if (c0 >= n) return;
+        pre(pc);
         const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
         // live row groups of this panel
         constexpr int S0 = (MODE == 0) ? p : 0;
@@ -407,6 +416,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                 });
             }
         }
+        post(pc);
     });
 
     const int n = opaque_s(n_);
@@ -637,13 +647,118 @@ __device__ __forceinline__ void tile_of_packed(T (&x)[NP][4][NP], const T* __res
 // wave waits for another and the levels need no separate launches.  The node
 // arithmetic does not depend on which child arrived last.
 struct TreeArgs {
-    int* cnt;        // W * levels counters, zero at launch
+    int* cnt;        // W * (levels + 1) counters, zero at launch
     void* Rout;      // final R (row-major, ldr), or null
     int64_t ldr;
     int zero_lower;  // also write zeros below R's diagonal
 };
 
-template <typename T, int NP, int SG>
+// ---- the panel-pipelined binary tree ----------------------------------------------
+//
+// When every wave of the launch is resident at once, a node need not wait for
+// its children to finish: panel p of the node [R_a; R_b] touches only R_a's
+// rows of panel p and R_b's rows of panels <= p, and a node's rows of panel p
+// are final as soon as its own panel p is done (a reflector of an earlier
+// panel acts on one row of R_a and on rows of R_b above the panel).  So each
+// level runs one panel behind the level below rather than one whole node.
+// Node (lev, i0) is performed by wave i0 + 2^(lev-1), the chain of its second
+// child, once that chain is done (a bijection between the chains 1..W-1 and
+// the nodes); it waits for its children's panels through progress counts
+// (lev * W + slot, zero at launch), published after the rows themselves.
+__device__ __forceinline__ void pub_flag(int* f, int v) {
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until *f >= v.  The producer is resident and never waits on this
+// wave, so it gets there; the bound only guarantees that the wave ends.
+__device__ __forceinline__ void wait_flag(const int* f, int v) {
+    for (int it = 0; it < (1 << 22); ++it) {
+        const int cur = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (cur >= v) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+// Level of the node that actually produces the R of tree position (l, idx):
+// positions with a single child pass their child's R up unchanged.
+__device__ __forceinline__ int producer_level(int W, int l, int idx) {
+    while (l > 0) {
+        const int st = 1 << (l - 1);
+        if ((W - idx + st - 1) / st >= 2) break;
+        --l;
+    }
+    return l;
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ Rbuf,
+                                               T* __restrict__ Ynode, T* __restrict__ Tnode,
+                                               T* __restrict__ tau_node, const TreeArgs& ta) {
+    constexpr int NCP = 16 * NP;
+    constexpr int RP = WSmem<T, NP>::RP;
+    const int n = (int)g.n;
+    const int W = g.W;
+    const int npl = (n + 15) / 16;  // live panels
+    const int64_t rs = rslot<NP>(n);
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    const int64_t nn = (int64_t)n * n;
+    int* prog = ta.cnt;
+    const int lane = lane_id();
+    // publish the chain's R (all panels at once)
+    r_pub<T, NP>(sm, Rbuf + (int64_t)c * rs);
+    pub_wait();
+    if (lane == 0) pub_flag(prog + c, npl);
+    if (c == 0) return;
+    const int lev = __builtin_ctz((unsigned)c) + 1;
+    const int i0 = c - (1 << (lev - 1));
+    const int la = producer_level(W, lev - 1, i0), lb = producer_level(W, lev - 1, c);
+    const bool own_b = lb == 0;  // the second child is this wave's own chain
+    T x[NP][4][NP];
+    if (own_b) {
+        tile_of_packed<T, NP>(x, sm.R, n);
+        wave_sync();
+    }
+    const T* Ra = Rbuf + (int64_t)i0 * rs;
+    const T* Rb = Rbuf + (int64_t)c * rs;
+    T* Rnode = Rbuf + (int64_t)i0 * rs;  // the node's R replaces child a's, panel by panel
+    auto pre = [&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int e0 = rpi<NCP>(16 * p, 16 * p);
+        constexpr int e1 = (p + 1 < NP) ? rpi<NCP>(16 * (p + 1), 16 * (p + 1)) : RP;
+        wait_flag(prog + la * W + i0, p + 1);
+        if (!own_b) wait_flag(prog + lb * W + c, p + 1);
+        for (int e = e0 + lane; e < e1; e += 64) sm.R[e] = pub_load(Ra + e);
+        if (!own_b) {
+            typedef Mfma<T> M;
+            const int l16 = lane & 15, l4 = lane >> 4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * p + M::orow(l4, i);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int cc = 16 * q + l16;
+                    const bool ok = q >= p && cc >= r && cc < n && r < n;
+                    const T v = pub_load(Rb + rpi<NCP>(ok ? r : 0, ok ? cc : 0));
+                    x[p][i][q] = ok ? v : T(0);
+                }
+            }
+        }
+        wave_sync();
+    };
+    auto post = [&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int e0 = rpi<NCP>(16 * p, 16 * p);
+        constexpr int e1 = (p + 1 < NP) ? rpi<NCP>(16 * (p + 1), 16 * (p + 1)) : RP;
+        wave_sync();
+        for (int e = e0 + lane; e < e1; e += 64) pub_store(Rnode + e, sm.R[e]);
+        pub_wait();
+        if (lane == 0) pub_flag(prog + lev * W + i0, p + 1);
+    };
+    auto emit = [&]() { wstore<T, NP, NP>(x, Ynode + (int64_t)c * nn, n, 0, n, n); };
+    wave_block<T, NP, NP, 2>(x, sm, n, Tnode + (int64_t)c * tri, tau_node + (int64_t)c * n, emit, pre, post);
+    if (lev == g.levels && ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
+}
+
+template <typename T, int NP, int SG, bool PIPE = false>
 __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ A, int64_t lda,
                                           T* __restrict__ tau_blk, T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                           T* __restrict__ Ynode, T* __restrict__ Tnode, T* __restrict__ tau_node,
@@ -673,6 +788,12 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         }
     }
     // ---- the tree
+    if constexpr (PIPE) {
+        if (g.W > 1) {
+            wave_tree_pipe<T, NP>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
+            return;
+        }
+    }
     const int64_t rs = rslot<NP>(n);
     int cur = c;
     for (int lev = 1; lev <= g.levels; ++lev) {

@@ -38,10 +38,10 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(block_rows=0, chains=0, arity=0):
-    if not (block_rows or chains or arity):
+def _opts(block_rows=0, chains=0, arity=0, flags=0):
+    if not (block_rows or chains or arity or flags):
         return None
-    o = _lib.opts(block_rows, chains, arity)
+    o = _lib.opts(block_rows, chains, arity, flags)
     return ctypes.byref(o)
 
 
@@ -114,17 +114,20 @@ class QTree:
             pass
 
 
-def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0):
+def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0,
+           levelwise: bool = False):
     """TSQR of A (m x n, m >= n, n <= 64), IN PLACE: A is overwritten by the
     leaf reflectors.  Returns (R, QTree); diag(R) carries the Householder
-    signs (see sign_normalize)."""
+    signs (see sign_normalize).  levelwise: reduce the tree node by node
+    (TSQR_FLAG_TREE_LEVELWISE) instead of panel-pipelined; same result."""
     lib = _lib.load()
     m, n = A.shape
     if R is None:
         R = torch.empty(n, n, dtype=A.dtype, device=A.device)
     h = ctypes.c_void_p()
+    flags = _lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0
     rc = lib.tsqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(R), _ld(R),
-                         _opts(block_rows, chains, arity), ctypes.byref(h), _stream(A))
+                         _opts(block_rows, chains, arity, flags), ctypes.byref(h), _stream(A))
     _lib.check("tsqr_factor", rc)
     return R, QTree(h, A, m, n)
 

@@ -53,7 +53,7 @@ def test_factor_argument_errors_without_launch():
     assert f(1, 100, 4, None, 4, fake, 4, None, ctypes.byref(h), None) == -4       # A
     assert f(1, 100, 4, fake, 3, fake, 4, None, ctypes.byref(h), None) == -5       # lda
     assert f(1, 100, 4, fake, 4, fake, 3, None, ctypes.byref(h), None) == -7       # ldr
-    bad = _lib.opts(flags=1)
+    bad = _lib.opts(flags=2)  # not a defined flag
     assert f(1, 100, 4, fake, 4, fake, 4, ctypes.byref(bad), ctypes.byref(h), None) == -8
     assert f(1, 100, 4, fake, 4, None, 4, None, None, None) == -9                  # nothing to return
     bad_h = _lib.opts(block_rows=100)

@@ -208,6 +208,38 @@ def test_tree_shape_invariance():
         assert oracle.rel_err(R, Rs[0]) <= 1e-13
 
 
+@pytest.mark.parametrize("m,n,chains,dt", [
+    (1 << 16, 64, 0, "f64"),      # 1024 chains of one block, 10 levels
+    (100000, 48, 37, "f64"),      # W not a power of two: unpaired positions
+    (70000, 17, 300, "f64"),      # two panels, the second with one live column
+    (50000, 8, 200, "f64"),       # one panel
+    (40000, 64, 3, "f64"),        # two levels, an unpaired chain at the top
+    (1 << 16, 64, 513, "f32"),
+])
+def test_pipelined_tree_matches_levelwise(m, n, chains, dt):
+    """The panel-pipelined tree and the node-by-node tree perform the same
+    node arithmetic in the same order: R, the reflectors and Q agree bitwise,
+    and R matches the oracle."""
+    import paper_0808_2664_amd as tq
+    _note("case: pipelined vs levelwise tree m=%d n=%d chains=%d %s" % (m, n, chains, dt))
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    A_np = workloads.gaussian(m, n, 21)
+    outs = []
+    for lw in (False, True):
+        A = _dev(A_np, dtype)
+        R, qt = tq.factor(A, chains=chains, levelwise=lw)
+        Q = qt.form_q()
+        torch.cuda.synchronize()
+        outs.append((R.clone(), A.clone(), Q))
+        qt.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+    g = _normalised(outs[0][0], outs[0][2])
+    o = _oracle(A_np, None)
+    assert oracle.rel_err(g["R"], o["R"]) <= (1e-11 if dt == "f64" else 5e-4)
+
+
 def test_f32_gaussian():
     _note("case: f32")
     A = workloads.gaussian(30000, 32, 12).astype(np.float32)
