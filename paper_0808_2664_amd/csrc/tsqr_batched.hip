@@ -73,7 +73,7 @@ static const void* batch_kernel(int cls) {
     switch (cls) {
         case 0: return (const void*)&k_batch_tsqr<T, 1, 2>;
         case 1: return (const void*)&k_batch_tsqr<T, 2, 2>;
-        default: return (const void*)&k_batch_tsqr<T, 4, 1>;
+        default: return (const void*)&k_batch_tsqr<T, 4, (sizeof(T) == 8 ? 1 : 2)>;
     }
 }
 
@@ -86,7 +86,9 @@ static hipError_t launch_batch_class(int cls, int grid, hipStream_t st, const BM
     switch (cls) {
         case 0: k_batch_tsqr<T, 1, 2><<<grid, 64, 0, st>>>(mats, items, nitems, next, a, lda, r, ldr); break;
         case 1: k_batch_tsqr<T, 2, 2><<<grid, 64, 0, st>>>(mats, items, nitems, next, a, lda, r, ldr); break;
-        default: k_batch_tsqr<T, 4, 1><<<grid, 64, 0, st>>>(mats, items, nitems, next, a, lda, r, ldr); break;
+        default:
+            k_batch_tsqr<T, 4, (sizeof(T) == 8 ? 1 : 2)><<<grid, 64, 0, st>>>(mats, items, nitems, next, a, lda, r, ldr);
+            break;
     }
     return hipGetLastError();
 }

@@ -9,17 +9,20 @@
 // finishes its last child (see tsqr_wave.hpp for the engine and the tree).
 #include "tsqr_wave.hpp"
 
-// Waves per SIMD the factor kernel is compiled for (register budget 512/occ).
-#ifndef TSQR_WAVE_OCC
-#define TSQR_WAVE_OCC 1
-#endif
-
 namespace tsqr {
+
+// Waves per SIMD the factor kernel is compiled for (register budget 512/occ):
+// the FP64 tile of a 64 x 64 block takes 128 registers per lane and the
+// kernel needs the whole file; the FP32 kernel fits two waves per SIMD.
+template <typename T>
+struct WaveOcc {
+    static constexpr int value = sizeof(T) == 8 ? 1 : 2;
+};
 
 // PIPE: the panel-pipelined binary tree; launched cooperatively, so that
 // every wave is resident and a node's wave may wait for its children.
 template <typename T, int NP, int SG, bool PIPE>
-__global__ __launch_bounds__(64, TSQR_WAVE_OCC) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
+__global__ __launch_bounds__(64, WaveOcc<T>::value) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
                                                      T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                                      T* __restrict__ Ynode, T* __restrict__ Tnode,
                                                      T* __restrict__ tau_node, TreeArgs ta) {

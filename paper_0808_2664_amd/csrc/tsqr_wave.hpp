@@ -775,12 +775,20 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         const int nb = chain_nblocks(g, c);
         const int64_t blk0 = chain_blk0(g, c);
         constexpr int H = 16 * SG;
+        // The next block is loaded as soon as this block's reflectors are
+        // stored, so its loads are in flight during the T products.
+        T x[SG][4][NP];
+        wload<T, NP, SG>(x, A, lda, start, (int)((end - start) < H ? (end - start) : H), n);
         for (int b = 0; b < nb; ++b) {
             const int64_t r0 = start + (int64_t)b * H;
             const int rows = (int)((end - r0) < H ? (end - r0) : H);
-            T x[SG][4][NP];
-            wload<T, NP, SG>(x, A, lda, r0, rows, n);
-            auto emit = [&]() { wstore<T, NP, SG>(x, A, lda, r0, rows, n); };
+            auto emit = [&]() {
+                wstore<T, NP, SG>(x, A, lda, r0, rows, n);
+                if (b + 1 < nb) {
+                    const int64_t r1 = r0 + H;
+                    wload<T, NP, SG>(x, A, lda, r1, (int)((end - r1) < H ? (end - r1) : H), n);
+                }
+            };
             if (b == 0)
                 wave_block<T, NP, SG, 0>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
             else
