@@ -288,27 +288,72 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     q->n = n;
     q->panel = panel;
     // Right-looking QR with TSQR panels (Sec. 3): factor panel k, then apply
-    // its implicit Q^T to the trailing columns (Sec. 3.1, leaf then tree level).
-    for (int64_t r0 = 0; r0 < n; r0 += panel) {
+    // its implicit Q^T to the trailing columns (Sec. 3.1, leaves then tree).
+    // Look-ahead: once panel k's update has reached the next panel's columns,
+    // panel k+1 is factored on a second stream while the rest of panel k's
+    // update proceeds; panel k+1's update waits for both.
+    // Panel trees: chains of a few blocks (the tree's node steps add to the
+    // trailing update what the leaves cost, so short chains double it), node
+    // by node (no waiting on a stream shared with the update).
+    const int chain_blocks = env_int("TSQR_CAQR_CHAIN_BLOCKS", 4);
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_head = nullptr, ev_fact = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_head, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming);
+    auto cleanup = [&]() {
+        if (ev_head) (void)hipEventDestroy(ev_head);
+        if (ev_fact) (void)hipEventDestroy(ev_fact);
+        if (s2) (void)hipStreamDestroy(s2);
+    };
+    auto panel_opts = [&](int64_t rows) {
+        tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0};
+        if (o.chains == 0) {
+            const int64_t blocks = (rows + 63) / 64;
+            const int64_t w = (blocks + chain_blocks - 1) / (chain_blocks > 0 ? chain_blocks : 1);
+            o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
+        }
+        o.flags |= TSQR_FLAG_TREE_LEVELWISE;
+        return o;
+    };
+    auto factor_panel = [&](int64_t r0, hipStream_t fs) -> int {
         const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
         const int64_t rows = m - r0;
         char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
+        tsqr_opts po = panel_opts(rows);
         tsqr_qtree_s* pq = nullptr;
-        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, opts, &pq, st);
-        if (rc != 0) {
-            destroy_impl(q);
-            return rc == -1 ? -2 : rc;
-        }
+        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, &po, &pq, fs);
+        if (rc != 0) return rc == -1 ? -2 : rc;
+        pq->stream = st;  // later applies and the release run on the caller's stream
         q->panels.push_back(pq);
+        return 0;
+    };
+    int rc = (e == hipSuccess) ? factor_panel(0, st) : hip_fail(e);
+    for (int64_t r0 = 0; rc == 0 && r0 < n; r0 += panel) {
+        const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
         const int64_t tc = n - r0 - cols;
-        if (tc > 0) {
-            hipError_t e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, P + (size_t)cols * es, lda,
-                                              tc, tsqr::MODE_QT, st);
-            if (e != hipSuccess) {
-                destroy_impl(q);
-                return hip_fail(e);
-            }
-        }
+        if (tc <= 0) break;
+        tsqr_qtree_s* pq = q->panels.back();
+        char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
+        char* Bt = P + (size_t)cols * es;
+        const int64_t head = tc < panel ? tc : panel;  // the next panel's columns
+        e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, Bt, lda, head, tsqr::MODE_QT, st);
+        if (e == hipSuccess) e = hipEventRecord(ev_head, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev_head, 0);
+        if (e != hipSuccess) { rc = hip_fail(e); break; }
+        rc = factor_panel(r0 + cols, s2);
+        if (rc != 0) break;
+        e = hipEventRecord(ev_fact, s2);
+        if (e == hipSuccess && tc > head)
+            e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, Bt + (size_t)head * es, lda, tc - head,
+                                   tsqr::MODE_QT, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_fact, 0);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
+    cleanup();
+    if (rc != 0) {
+        destroy_impl(q);
+        return rc;
     }
     if (q_out) *q_out = q;
     else destroy_impl(q);
