@@ -49,11 +49,13 @@ struct Apply64Smem {
     C trans[4][16][17];    // per-wave transposes
 };
 
+// Held in the storage type: a prefetched value is converted to the compute
+// type only where it is used, so the load's latency stays hidden.
 template <typename S, typename C, int NP, int MODE>
 struct Apply64Regs {
-    C y[4][NP];  // Y rows 16w + orow(l4, i), columns 16p + l16
-    C x[4];      // B rows 16w + orow(l4, i), column col
-    C t[NP][4];  // T fragments of this wave's W' tile (A-operand layout)
+    S y[4][NP];  // Y rows 16w + orow(l4, i), columns 16p + l16
+    S x[4];      // B rows 16w + orow(l4, i), column col
+    S t[NP][4];  // T fragments of this wave's W' tile (A-operand layout)
 };
 
 // PUB: the rows of B were published by another workgroup of this launch.
@@ -69,12 +71,12 @@ __device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int cc = 16 * p + l16;
-            C v = (r < rows && cc < n) ? (C)Y[(r0 + r) * ldy + cc] : C(0);
-            if (top) v = (cc < n) ? vunit(v, r, cc) : C(0);
+            S v = (r < rows && cc < n) ? Y[(r0 + r) * ldy + cc] : S(0);
+            if (top) v = (cc < n) ? vunit(v, r, cc) : S(0);
             R.y[i][p] = v;
         }
         const S* bp = B + (r0 + r) * ldb + col;
-        R.x[i] = (MODE != MODE_FORMQ && r < rows && colok) ? (C)(PUB ? pub_load(bp) : *bp) : C(0);
+        R.x[i] = (MODE != MODE_FORMQ && r < rows && colok) ? (PUB ? pub_load(bp) : *bp) : S(0);
     }
     // T fragments for output tile p = wv: QT uses (T_qp)^T (q <= p), Q uses T_pq (q >= p)
 #pragma unroll
@@ -90,7 +92,7 @@ __device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int
                 tj = 16 * q + M::orow(l4, kc);
             }
             const bool ok = wv < NP && ti <= tj && tj < n;
-            R.t[q][kc] = ok ? (C)Tb[(int64_t)tj * (tj + 1) / 2 + ti] : C(0);
+            R.t[q][kc] = ok ? Tb[(int64_t)tj * (tj + 1) / 2 + ti] : S(0);
         }
 }
 
@@ -106,7 +108,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * wv + M::orow(l4, i);
-            if (r < n) R.x[i] = sl[i];
+            if (r < n) R.x[i] = (S)sl[i];
         }
     }
     // Explicit Q, blocks past the first: the block's rows of B are zero, so
@@ -127,7 +129,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int p = 0; p < NP; ++p) acc[p] = M::mma(R.y[i][p], R.x[i], acc[p]);
+                for (int p = 0; p < NP; ++p) acc[p] = M::mma((C)R.y[i][p], (C)R.x[i], acc[p]);
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -156,7 +158,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 if (MODE == MODE_QT ? (q > wv) : (q < wv)) continue;
-                nw = M::mma(-R.t[q][kc], sm.part[0][q][kc][lane], nw);
+                nw = M::mma(-(C)R.t[q][kc], sm.part[0][q][kc][lane], nw);
             }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -167,11 +169,11 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
     __syncthreads();
     // 4. X -= Y W'
     {
-        acc_t u = acc_t{R.x[0], R.x[1], R.x[2], R.x[3]};
+        acc_t u = acc_t{(C)R.x[0], (C)R.x[1], (C)R.x[2], (C)R.x[3]};
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sm.trans[wv][M::orow(l4, i)][l16] = R.y[i][p];
+            for (int i = 0; i < 4; ++i) sm.trans[wv][M::orow(l4, i)][l16] = (C)R.y[i][p];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             C yt[4];
