@@ -247,7 +247,8 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                 hc = sum4((l4 == hl4) ? hv : T(0));
             } else {
                 alpha = sm.R[rpi<NCP>(j, j)];
-                const T hr = sm.R[rpi<NCP>(j, (c > j) ? c : j)];
+                T hr = sm.R[rpi<NCP>(j, (c > j) ? c : j)];
+                asm volatile("" : "+v"(hr));  // an unconditional load, not a branch around one
                 hc = (c > j && c < n) ? hr : T(0);
             }
             // column j, broadcast to the lanes of the other columns (tail rows only)
@@ -277,7 +278,10 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             const T tw = tau * w;
             const T coef = trail ? -tw * scale : T(0);
             if constexpr (MODE != 0) {
-                if (l4 == 0 && c >= j && c < n) sm.R[rpi<NCP>(j, (c > j) ? c : j)] = (c == j) ? beta : hc - tw;
+                // every lane stores (the four lanes of a column hold the same
+                // value); lanes left of the diagonal write into the staging tile
+                T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&sm.scr[0][0] + l16);
+                *dst = (c == j) ? beta : hc - tw;
             }
             sfor<S0, S1>([&](auto sc) {
                 constexpr int s = decltype(sc)::value;
@@ -301,7 +305,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                 constexpr int k = decltype(kc)::value;
                 t = fma(sm.td[p][l16][k], bcast16<k>(pw), t);
             });
-            if (l4 == 0) sm.td[p][l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
+            sm.td[p][l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
         });
 
         // reflector tails: scale the panel's columns (delayed from the sweep)
