@@ -52,6 +52,8 @@ def parse():
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, CAQR and forward+backward measurements")
+    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd"), default=None,
+                   help="run only this measurement and print its JSON (for profiling it)")
     return p.parse_args()
 
 
@@ -117,6 +119,11 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if a.extra:
+        import paper_0808_2664_amd as tq_x
+        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd}[a.extra]
+        print(json.dumps({a.extra: fn(tq_x, torch, np)}), flush=True)
+        return
 
     import workloads
     import paper_0808_2664_amd as tq
