@@ -70,17 +70,24 @@ __global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restr
         }
 }
 
-// G[b] = sum over chunks (fixed order) of the partials.
+// G[b] = sum over chunks of the partials, in a fixed order: wave w of a
+// workgroup adds chunks w, w + 4, w + 8, ... for 64 consecutive entries (one
+// per lane, so the loads are coalesced), then the four wave sums are added in
+// order.  Four independent streams per entry keep the loads in flight.
 template <typename T, int NC>
-__global__ void k_gram_reduce(int nch, const T* __restrict__ part, T* __restrict__ G) {
+__global__ __launch_bounds__(256) void k_gram_reduce(int nch, const T* __restrict__ part, T* __restrict__ G) {
     constexpr int NCP = NC < 16 ? 16 : NC;
+    __shared__ T red[4][64];
     const int b = blockIdx.y;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NCP * NCP) return;
-    const T* p = part + (int64_t)b * nch * NCP * NCP + e;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const bool ok = e < NCP * NCP;
+    const T* p = part + (int64_t)b * nch * NCP * NCP + (ok ? e : 0);
     T s = T(0);
-    for (int c = 0; c < nch; ++c) s += p[(int64_t)c * NCP * NCP];
-    G[(int64_t)b * NCP * NCP + e] = s;
+    for (int c = wv; c < nch; c += 4) s += p[(int64_t)c * NCP * NCP];
+    red[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && ok) G[(int64_t)b * NCP * NCP + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Per matrix: X = copyltu(R triu(dR)^T - G) R^{-T} and Y = R^{-T}.
@@ -230,7 +237,7 @@ static hipError_t backward_nc(int64_t batch, int64_t m, int n, const T* Q, int64
     T* XY = G + (size_t)batch * NCP * NCP;
     if (dQ) {
         k_gram<T, NC><<<dim3((unsigned)nch, (unsigned)batch), 256, 0, st>>>(m, n, dQ, lddq, sdq, Q, ldq, sq, CR, part);
-        k_gram_reduce<T, NC><<<dim3((NCP * NCP + 255) / 256, (unsigned)batch), 256, 0, st>>>((int)nch, part, G);
+        k_gram_reduce<T, NC><<<dim3((NCP * NCP + 63) / 64, (unsigned)batch), 256, 0, st>>>((int)nch, part, G);
     }
     k_adjoint_small<T, NC><<<(unsigned)batch, 256, 0, st>>>(n, R, ldr, sr, dR, lddr, sdr, G, dQ ? 1 : 0, XY);
     k_adjoint_stream<T, NC><<<dim3((unsigned)((m + 255) / 256), (unsigned)batch), 256, 0, st>>>(
