@@ -215,6 +215,8 @@ def test_tree_shape_invariance():
     (50000, 8, 200, "f64"),       # one panel
     (40000, 64, 3, "f64"),        # two levels, an unpaired chain at the top
     (1 << 16, 64, 513, "f32"),
+    (150000, 8, 2000, "f64"),     # 2000 waves, two per SIMD, still all resident
+    (200000, 64, 2000, "f64"),    # more chains than resident waves: node-by-node fallback
 ])
 def test_pipelined_tree_matches_levelwise(m, n, chains, dt):
     """The panel-pipelined tree and the node-by-node tree perform the same
