@@ -22,6 +22,8 @@
 // Q^T runs the chains in one launch and every tree level in a second one;
 // Q and the explicit Q run the tree levels top-down, one launch per level,
 // then the chains.
+#include <type_traits>
+
 #include "tsqr_common.hpp"
 
 namespace tsqr {
@@ -315,6 +317,201 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
     }
 }
 
+// ---- wide chain kernel: FP64, n = 64, 64 columns of B per workgroup ---------
+//
+// Each of the four waves owns one 16-column tile of B over all 64 rows of a
+// block, so W = V^T [S; X], W' = T^T W (Q^T) or T W (Q), S -= W' and
+// X -= Y W' need no reduction across waves: the rows of X sit in the MFMA B
+// operand layout, which for FP64 is also the accumulator layout
+// (x[kk] = row 4 kk + l4), and W and W' are used as B operands exactly as the
+// products leave them.  The block's Y (64 x 64, row pitch 66) and packed T are
+// staged once per workgroup in LDS, read as A operands, and the next block's
+// are loaded into registers while the current one is processed.
+// One wave per SIMD: the whole register file lets the LDS operand reads run
+// far ahead of the MFMAs that consume them.
+#ifndef WIDE_OCC
+#define WIDE_OCC 1
+#endif
+constexpr int WY_PITCH = 66;
+constexpr int W_TRI = 64 * 65 / 2;
+
+struct WideSmem {
+    double Y[64][WY_PITCH];
+    double T[W_TRI];
+};
+
+// Entry (i, j), i <= j, of the block's T (packed column by column).
+__device__ __forceinline__ double wide_t(const WideSmem& sm, int i, int j) { return sm.T[j * (j + 1) / 2 + i]; }
+
+template <int MODE>
+__global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const double* __restrict__ Y, int64_t ldy,
+                                                          const double* __restrict__ T_blk, double* __restrict__ B,
+                                                          int64_t ldb, int64_t k, int ngroups) {
+    typedef Mfma<double> M;
+    typedef M::acc acc_t;
+    __shared__ WideSmem sm;
+    const int gid = blockIdx.x;
+    const int x8 = gid & 7, yq = gid >> 3;
+    const int chain = (yq / ngroups) * 8 + x8;
+    const int grp = yq - (yq / ngroups) * ngroups;
+    if (chain >= g.W) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)grp * 64 + 16 * wv + l16;
+    const bool colok = col < k;
+    const int64_t start = chain_start(g, chain), end = chain_end(g, chain);
+    const int nb = chain_nblocks(g, chain);
+    const int64_t blk0 = chain_blk0(g, chain);
+    auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
+    // staging of one block's Y (rows 4t + wv, column lane) and packed T
+    double ys[16], ts[9];
+    auto stage_load = [&](int bi) {
+        const int b = blk(bi);
+        const int64_t r0 = start + (int64_t)b * 64;
+        const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int r = 4 * t + wv;
+            ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : 0.0;
+        }
+        const double* Tb = T_blk + (blk0 + b) * W_TRI;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int e = tid + 256 * t;
+            ts[t] = (e < W_TRI) ? Tb[e] : 0.0;
+        }
+    };
+    auto stage_store = [&](int bi) {
+        const bool top = blk(bi) == 0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int r = 4 * t + wv;
+            sm.Y[r][lane] = top ? vunit(ys[t], r, lane) : ys[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int e = tid + 256 * t;
+            if (e < W_TRI) sm.T[e] = ts[t];
+        }
+    };
+    // rows of B: x[kk] = row 4 kk + l4 of the block
+    double x[16], xn[16];
+    auto x_load = [&](double (&dst)[16], int bi) {
+        const int b = blk(bi);
+        const int64_t r0 = start + (int64_t)b * 64;
+        const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+        const bool zero = (MODE == MODE_FORMQ) || (MODE != MODE_QT && b == 0);  // zero rows / the slab
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int r = 4 * kk + l4;
+            dst[kk] = (!zero && r < rows && colok) ? B[(r0 + r) * ldb + col] : 0.0;
+        }
+    };
+    // slab S: rows 16p + 4i + l4 (the chain's first 64 rows)
+    acc_t sl[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * p + M::orow(l4, i);
+            sl[p][i] = (MODE != MODE_QT && colok) ? B[(start + r) * ldb + col] : 0.0;
+        }
+    stage_load(0);
+    x_load(x, 0);
+    stage_store(0);
+    __syncthreads();
+    for (int bi = 0; bi < nb; ++bi) {
+        const int b = blk(bi);
+        const bool top = b == 0;
+        const bool more = bi + 1 < nb;
+        // the first block in the Q direction holds the slab in its rows
+        if (MODE != MODE_QT && top) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[4 * p + i] = sl[p][i];
+        }
+        // W = V^T [S; X]
+        acc_t w[4];
+        const bool xzero = (MODE == MODE_FORMQ) && !top;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            w[p] = top ? acc_t{0, 0, 0, 0} : sl[p];
+            if (!xzero) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[4 * kk + l4][16 * p + l16], x[kk], w[p]);
+            }
+        }
+        // W' = T^T W (Q^T) or T W (Q); kept negated
+        acc_t nw[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            nw[p] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    const int ti = 16 * q + M::orow(l4, kc);  // = 16 q + 4 kc + l4
+                    const int tj = 16 * p + l16;
+                    const double a = (MODE == MODE_QT) ? ((ti <= tj) ? wide_t(sm, ti, tj) : 0.0)
+                                                       : ((tj <= ti) ? wide_t(sm, tj, ti) : 0.0);
+                    nw[p] = M::mma(-a, w[q][kc], nw[p]);
+                }
+            }
+        }
+        // S -= W'
+        if (!top) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+        }
+        // the next block's loads fly during X -= Y W' (issued here rather than
+        // earlier to keep the W product's registers free)
+        if (more) {
+            stage_load(bi + 1);
+            x_load(xn, bi + 1);
+        }
+        // X -= Y W'
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+        }
+        if (MODE == MODE_QT && top) {
+            // the chain's first block becomes the slab
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sl[p][i] = x[4 * p + i];
+        } else {
+            const int64_t r0 = start + (int64_t)b * 64;
+            const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int r = 4 * kk + l4;
+                if (r < rows && colok) B[(r0 + r) * ldb + col] = x[kk];
+            }
+        }
+        if (more) {
+            __syncthreads();  // every wave is done with this block's Y and T
+            stage_store(bi + 1);
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) x[kk] = xn[kk];
+        }
+    }
+    if (MODE == MODE_QT && colok) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) B[(start + 16 * p + M::orow(l4, i)) * ldb + col] = sl[p][i];
+    }
+}
+
 __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -338,6 +535,15 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
     phase_begin(1 + MODE, st);
     static_assert(H == 64, "the chain kernel takes 64-row blocks");
+    if constexpr (std::is_same<S, double>::value && std::is_same<C, double>::value && NP == 4) {
+        if (g.n == 64 && k >= 64) {
+            const int ngroups = (int)((k + 63) / 64);
+            const int64_t gw = (int64_t)groups * 8 * ngroups;
+            k_chain_apply_w<MODE><<<(int)gw, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ngroups);
+            phase_end(1 + MODE, st);
+            return hipGetLastError();
+        }
+    }
     k_chain_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ntiles);
     phase_end(1 + MODE, st);
     return hipGetLastError();
