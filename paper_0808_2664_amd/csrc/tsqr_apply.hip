@@ -317,39 +317,42 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
     }
 }
 
-// ---- wide chain kernel: FP64, n = 64, 64 columns of B per workgroup ---------
+// ---- wide chain kernel: n = 64, 64 columns of B per workgroup ---------------
 //
 // Each of the four waves owns one 16-column tile of B over all 64 rows of a
 // block, so W = V^T [S; X], W' = T^T W (Q^T) or T W (Q), S -= W' and
-// X -= Y W' need no reduction across waves: the rows of X sit in the MFMA B
-// operand layout, which for FP64 is also the accumulator layout
-// (x[kk] = row 4 kk + l4), and W and W' are used as B operands exactly as the
-// products leave them.  The block's Y (64 x 64, row pitch 66) and packed T are
-// staged once per workgroup in LDS, read as A operands, and the next block's
-// are loaded into registers while the current one is processed.
-// One wave per SIMD: the whole register file lets the LDS operand reads run
-// far ahead of the MFMAs that consume them.
-#ifndef WIDE_OCC
-#define WIDE_OCC 1
-#endif
+// X -= Y W' need no reduction across waves.  The block's rows of X are held
+// in the MFMA accumulator layout (x[4r + i] = row 16r + orow(l4, i)); the
+// V^T X product sums over the rows in that same order, so x is also its B
+// operand, and W and W' are used as B operands exactly as the products leave
+// them: no transposes.  The block's Y (64 x 64, row pitch 66) and packed T
+// are staged once per workgroup in LDS (in the compute type) and read as A
+// operands; the next block's Y, T and rows of B are loaded into registers
+// (in the storage type) while the current block is processed.
+// One wave per SIMD (two for the FP32 Q and explicit-Q forms): the register
+// file lets the LDS operand reads run far ahead of the MFMAs that use them.
 constexpr int WY_PITCH = 66;
 constexpr int W_TRI = 64 * 65 / 2;
 
+template <typename C>
 struct WideSmem {
-    double Y[64][WY_PITCH];
-    double T[W_TRI];
+    C Y[64][WY_PITCH];
+    C T[W_TRI];
 };
 
 // Entry (i, j), i <= j, of the block's T (packed column by column).
-__device__ __forceinline__ double wide_t(const WideSmem& sm, int i, int j) { return sm.T[j * (j + 1) / 2 + i]; }
+template <typename C>
+__device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
+    return sm.T[j * (j + 1) / 2 + i];
+}
 
-template <int MODE>
-__global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const double* __restrict__ Y, int64_t ldy,
-                                                          const double* __restrict__ T_blk, double* __restrict__ B,
+template <typename S, typename C, int MODE>
+__global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) void k_chain_apply_w(Geom g, const S* __restrict__ Y, int64_t ldy,
+                                                          const S* __restrict__ T_blk, S* __restrict__ B,
                                                           int64_t ldb, int64_t k, int ngroups) {
-    typedef Mfma<double> M;
-    typedef M::acc acc_t;
-    __shared__ WideSmem sm;
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    __shared__ WideSmem<C> sm;
     const int gid = blockIdx.x;
     const int x8 = gid & 7, yq = gid >> 3;
     const int chain = (yq / ngroups) * 8 + x8;
@@ -362,8 +365,10 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
     const int nb = chain_nblocks(g, chain);
     const int64_t blk0 = chain_blk0(g, chain);
     auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
+    // row of register kk = 4r + i of the accumulator layout
+    auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
     // staging of one block's Y (rows 4t + wv, column lane) and packed T
-    double ys[16], ts[9];
+    S ys[16], ts[9];
     auto stage_load = [&](int bi) {
         const int b = blk(bi);
         const int64_t r0 = start + (int64_t)b * 64;
@@ -371,13 +376,13 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int r = 4 * t + wv;
-            ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : 0.0;
+            ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : S(0);
         }
-        const double* Tb = T_blk + (blk0 + b) * W_TRI;
+        const S* Tb = T_blk + (blk0 + b) * W_TRI;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int e = tid + 256 * t;
-            ts[t] = (e < W_TRI) ? Tb[e] : 0.0;
+            ts[t] = (e < W_TRI) ? Tb[e] : S(0);
         }
     };
     auto stage_store = [&](int bi) {
@@ -385,40 +390,42 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int r = 4 * t + wv;
-            sm.Y[r][lane] = top ? vunit(ys[t], r, lane) : ys[t];
+            sm.Y[r][lane] = (C)(top ? vunit(ys[t], r, lane) : ys[t]);
         }
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int e = tid + 256 * t;
-            if (e < W_TRI) sm.T[e] = ts[t];
+            if (e < W_TRI) sm.T[e] = (C)ts[t];
         }
     };
-    // rows of B: x[kk] = row 4 kk + l4 of the block
-    double x[16], xn[16];
-    auto x_load = [&](double (&dst)[16], int bi) {
+    S xn[16];
+    auto x_load = [&](int bi) {
         const int b = blk(bi);
         const int64_t r0 = start + (int64_t)b * 64;
         const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
         const bool zero = (MODE == MODE_FORMQ) || (MODE != MODE_QT && b == 0);  // zero rows / the slab
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-            const int r = 4 * kk + l4;
-            dst[kk] = (!zero && r < rows && colok) ? B[(r0 + r) * ldb + col] : 0.0;
+            const int r = xrow(kk);
+            xn[kk] = (!zero && r < rows && colok) ? B[(r0 + r) * ldb + col] : S(0);
         }
     };
-    // slab S: rows 16p + 4i + l4 (the chain's first 64 rows)
+    // slab S (the chain's first 64 rows), accumulator layout
     acc_t sl[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * p + M::orow(l4, i);
-            sl[p][i] = (MODE != MODE_QT && colok) ? B[(start + r) * ldb + col] : 0.0;
+            sl[p][i] = (MODE != MODE_QT && colok) ? (C)B[(start + r) * ldb + col] : C(0);
         }
+    C x[16];
     stage_load(0);
-    x_load(x, 0);
+    x_load(0);
     stage_store(0);
     __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) x[kk] = (C)xn[kk];
     for (int bi = 0; bi < nb; ++bi) {
         const int b = blk(bi);
         const bool top = b == 0;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
             w[p] = top ? acc_t{0, 0, 0, 0} : sl[p];
             if (!xzero) {
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[4 * kk + l4][16 * p + l16], x[kk], w[p]);
+                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
             }
         }
         // W' = T^T W (Q^T) or T W (Q); kept negated
@@ -451,10 +458,10 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
                 if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
 #pragma unroll
                 for (int kc = 0; kc < 4; ++kc) {
-                    const int ti = 16 * q + M::orow(l4, kc);  // = 16 q + 4 kc + l4
+                    const int ti = 16 * q + M::orow(l4, kc);
                     const int tj = 16 * p + l16;
-                    const double a = (MODE == MODE_QT) ? ((ti <= tj) ? wide_t(sm, ti, tj) : 0.0)
-                                                       : ((tj <= ti) ? wide_t(sm, tj, ti) : 0.0);
+                    const C a = (MODE == MODE_QT) ? ((ti <= tj) ? wide_t(sm, ti, tj) : C(0))
+                                                  : ((tj <= ti) ? wide_t(sm, tj, ti) : C(0));
                     nw[p] = M::mma(-a, w[q][kc], nw[p]);
                 }
             }
@@ -464,11 +471,10 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
 #pragma unroll
             for (int p = 0; p < 4; ++p) sl[p] += nw[p];
         }
-        // the next block's loads fly during X -= Y W' (issued here rather than
-        // earlier to keep the W product's registers free)
+        // the next block's loads fly during X -= Y W'
         if (more) {
             stage_load(bi + 1);
-            x_load(xn, bi + 1);
+            x_load(bi + 1);
         }
         // X -= Y W'
 #pragma unroll
@@ -492,8 +498,8 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
             const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
-                const int r = 4 * kk + l4;
-                if (r < rows && colok) B[(r0 + r) * ldb + col] = x[kk];
+                const int r = xrow(kk);
+                if (r < rows && colok) B[(r0 + r) * ldb + col] = (S)x[kk];
             }
         }
         if (more) {
@@ -501,14 +507,14 @@ __global__ __launch_bounds__(256, WIDE_OCC) void k_chain_apply_w(Geom g, const d
             stage_store(bi + 1);
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) x[kk] = xn[kk];
+            for (int kk = 0; kk < 16; ++kk) x[kk] = (C)xn[kk];
         }
     }
     if (MODE == MODE_QT && colok) {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) B[(start + 16 * p + M::orow(l4, i)) * ldb + col] = sl[p][i];
+            for (int i = 0; i < 4; ++i) B[(start + 16 * p + M::orow(l4, i)) * ldb + col] = (S)sl[p][i];
     }
 }
 
@@ -535,11 +541,11 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
     phase_begin(1 + MODE, st);
     static_assert(H == 64, "the chain kernel takes 64-row blocks");
-    if constexpr (std::is_same<S, double>::value && std::is_same<C, double>::value && NP == 4) {
+    if constexpr (NP == 4) {
         if (g.n == 64 && k >= 64) {
             const int ngroups = (int)((k + 63) / 64);
             const int64_t gw = (int64_t)groups * 8 * ngroups;
-            k_chain_apply_w<MODE><<<(int)gw, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ngroups);
+            k_chain_apply_w<S, C, MODE><<<(int)gw, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ngroups);
             phase_end(1 + MODE, st);
             return hipGetLastError();
         }
