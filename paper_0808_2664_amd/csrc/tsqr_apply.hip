@@ -518,6 +518,125 @@ __global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) v
     }
 }
 
+// Tree levels of Q^T for n = 64 with 64 columns per workgroup, as
+// k_qt_tree64 (level-1 node per workgroup, then the last arrival performs a
+// node), each wave owning a 16-column tile over all 64 slab rows as in
+// k_chain_apply_w; a step's Y_node and T_node are staged in LDS.
+template <typename S, typename C>
+__global__ __launch_bounds__(256, 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb, int64_t k,
+                                                      const S* __restrict__ Ynode, const S* __restrict__ Tnode,
+                                                      int* __restrict__ cnt) {
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    __shared__ WideSmem<C> sm;
+    __shared__ int s_old;
+    const int node = blockIdx.x / ngroups;
+    const int grp = blockIdx.x - node * ngroups;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)grp * 64 + 16 * wv + l16;
+    const bool colok = col < k;
+    auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
+    int cur = node * g.arity;
+    if (cur >= g.W) return;
+    bool staged = false;  // LDS holds a previous step's operands
+    for (int lev = 1; lev <= g.levels; ++lev) {
+        const int64_t stride = ipow(g.arity, lev - 1);
+        const int64_t span = stride * g.arity;
+        const int i0 = (int)((cur / span) * span);
+        int nch = (int)((g.W - i0 + stride - 1) / stride);
+        if (nch > g.arity) nch = g.arity;
+        if (nch <= 1) continue;  // unpaired: carried up unchanged
+        if (lev > 1) {
+            pub_wait();  // this workgroup's slab stores have landed
+            __syncthreads();
+            if (tid == 0) s_old = atomicAdd(cnt + (((int64_t)(lev - 2) * g.W + i0) * ngroups + grp), 1);
+            __syncthreads();
+            if (s_old != nch - 1) return;
+        }
+        const int64_t sa = chain_start(g, i0);
+        acc_t sl[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                sl[p][i] = colok ? (C)pub_load(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col) : C(0);
+        for (int t = 1; t < nch; ++t) {
+            const int64_t ch = i0 + t * stride;
+            S* Bc = B + chain_start(g, (int)ch) * ldb;
+            // stage Y_node (64 x 64, row-major) and T_node
+            S ys[16], ts[9];
+            const S* Yc = Ynode + ch * 4096;
+            const S* Tc = Tnode + ch * W_TRI;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) ys[u] = Yc[(4 * u + wv) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                const int e = tid + 256 * u;
+                ts[u] = (e < W_TRI) ? Tc[e] : S(0);
+            }
+            C x[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) x[kk] = colok ? (C)pub_load(Bc + xrow(kk) * ldb + col) : C(0);
+            if (staged) __syncthreads();  // every wave is done with the previous step's operands
+#pragma unroll
+            for (int u = 0; u < 16; ++u) sm.Y[4 * u + wv][lane] = (C)ys[u];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                const int e = tid + 256 * u;
+                if (e < W_TRI) sm.T[e] = (C)ts[u];
+            }
+            __syncthreads();
+            staged = true;
+            // W = S + Y^T X;  W' = T^T W (negated);  S -= W';  X -= Y W'
+            acc_t w[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                w[p] = sl[p];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+            }
+            acc_t nw[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                nw[p] = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q <= p; ++q)
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) {
+                        const int ti = 16 * q + M::orow(l4, kc);
+                        const int tj = 16 * p + l16;
+                        const C a = (ti <= tj) ? wide_t(sm, ti, tj) : C(0);
+                        nw[p] = M::mma(-a, w[q][kc], nw[p]);
+                    }
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+            }
+            if (colok) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = (S)x[kk];
+            }
+        }
+        if (colok) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pub_store(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col, (S)sl[p][i]);
+        }
+        cur = i0;
+    }
+}
+
 __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -561,15 +680,20 @@ template <typename S, typename C, int NC>
 static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ldb, int64_t k, hipStream_t st) {
     if (g.levels == 0) return hipSuccess;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
-    const int ntiles = (int)((k + 15) / 16);
+    const bool wide = NP == 4 && g.n == 64 && k >= 64;
+    const int ntiles = wide ? (int)((k + 63) / 64) : (int)((k + 15) / 16);  // column groups of the launch
     const int64_t nodes = (g.W + g.arity - 1) / g.arity;
     int* cnt = nullptr;
     const int64_t ncnt = (int64_t)g.W * (g.levels > 1 ? g.levels - 1 : 1) * ntiles;
     hipError_t e = hipMallocAsync((void**)&cnt, (size_t)ncnt * sizeof(int), st);
     if (e != hipSuccess) return e;
     k_apply_zero<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(cnt, ncnt);
-    k_qt_tree64<S, C, NP><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
-                                                                       (const S*)wk.Tnode, cnt);
+    if (wide)
+        k_qt_tree_w<S, C><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
+                                                                     (const S*)wk.Tnode, cnt);
+    else
+        k_qt_tree64<S, C, NP><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
+                                                                           (const S*)wk.Tnode, cnt);
     e = hipGetLastError();
     hipError_t e2 = hipFreeAsync(cnt, st);
     return e != hipSuccess ? e : e2;

@@ -293,9 +293,12 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // panel k+1 is factored on a second stream while the rest of panel k's
     // update proceeds; panel k+1's update waits for both.
     // Panel trees: chains of a few blocks (the tree's node steps add to the
-    // trailing update what the leaves cost, so short chains double it), node
+    // trailing update what the leaves cost, so one-block chains double it;
+    // longer chains lengthen the panel factorisation, which the look-ahead
+    // hides only behind a long enough update): eight blocks for panels of
+    // 12288 rows or more, four below (measured on 8192^2 and 16384^2), node
     // by node (no waiting on a stream shared with the update).
-    const int chain_blocks = env_int("TSQR_CAQR_CHAIN_BLOCKS", 4);
+    const int chain_blocks_env = env_int("TSQR_CAQR_CHAIN_BLOCKS", 0);
     hipStream_t s2 = nullptr;
     hipEvent_t ev_head = nullptr, ev_fact = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
@@ -310,7 +313,8 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0};
         if (o.chains == 0) {
             const int64_t blocks = (rows + 63) / 64;
-            const int64_t w = (blocks + chain_blocks - 1) / (chain_blocks > 0 ? chain_blocks : 1);
+            const int chain_blocks = chain_blocks_env > 0 ? chain_blocks_env : (rows >= 12288 ? 8 : 4);
+            const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
         }
         o.flags |= TSQR_FLAG_TREE_LEVELWISE;
