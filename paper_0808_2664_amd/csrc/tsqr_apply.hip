@@ -346,10 +346,12 @@ __device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
     return sm.T[j * (j + 1) / 2 + i];
 }
 
-template <typename S, typename C, int MODE>
-__global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) void k_chain_apply_w(Geom g, const S* __restrict__ Y, int64_t ldy,
-                                                          const S* __restrict__ T_blk, S* __restrict__ B,
-                                                          int64_t ldb, int64_t k, int ngroups) {
+// TW waves per workgroup (2 or 4), so 16 TW columns of B per workgroup.
+template <typename S, typename C, int MODE, int TW>
+__global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW == 4) ? 2 : 1) void k_chain_apply_w(
+    Geom g, const S* __restrict__ Y, int64_t ldy, const S* __restrict__ T_blk, S* __restrict__ B, int64_t ldb, int64_t k,
+    int ngroups) {
+    constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
     typedef Mfma<C> M;
     typedef typename M::acc acc_t;
     __shared__ WideSmem<C> sm;
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) v
     const int grp = yq - (yq / ngroups) * ngroups;
     if (chain >= g.W) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
-    const int64_t col = (int64_t)grp * 64 + 16 * wv + l16;
+    const int64_t col = (int64_t)grp * (16 * TW) + 16 * wv + l16;
     const bool colok = col < k;
     const int64_t start = chain_start(g, chain), end = chain_end(g, chain);
     const int nb = chain_nblocks(g, chain);
@@ -367,34 +369,34 @@ __global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) v
     auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
     // row of register kk = 4r + i of the accumulator layout
     auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
-    // staging of one block's Y (rows 4t + wv, column lane) and packed T
-    S ys[16], ts[9];
+    // staging of one block's Y (rows TW t + wv, column lane) and packed T
+    S ys[YS], ts[TSN];
     auto stage_load = [&](int bi) {
         const int b = blk(bi);
         const int64_t r0 = start + (int64_t)b * 64;
         const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int r = 4 * t + wv;
+        for (int t = 0; t < YS; ++t) {
+            const int r = TW * t + wv;
             ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : S(0);
         }
         const S* Tb = T_blk + (blk0 + b) * W_TRI;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int e = tid + 256 * t;
+        for (int t = 0; t < TSN; ++t) {
+            const int e = tid + NT * t;
             ts[t] = (e < W_TRI) ? Tb[e] : S(0);
         }
     };
     auto stage_store = [&](int bi) {
         const bool top = blk(bi) == 0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int r = 4 * t + wv;
+        for (int t = 0; t < YS; ++t) {
+            const int r = TW * t + wv;
             sm.Y[r][lane] = (C)(top ? vunit(ys[t], r, lane) : ys[t]);
         }
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int e = tid + 256 * t;
+        for (int t = 0; t < TSN; ++t) {
+            const int e = tid + NT * t;
             if (e < W_TRI) sm.T[e] = (C)ts[t];
         }
     };
@@ -522,10 +524,11 @@ __global__ __launch_bounds__(256, (sizeof(C) == 4 && MODE != MODE_QT) ? 2 : 1) v
 // k_qt_tree64 (level-1 node per workgroup, then the last arrival performs a
 // node), each wave owning a 16-column tile over all 64 slab rows as in
 // k_chain_apply_w; a step's Y_node and T_node are staged in LDS.
-template <typename S, typename C>
-__global__ __launch_bounds__(256, 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb, int64_t k,
-                                                      const S* __restrict__ Ynode, const S* __restrict__ Tnode,
-                                                      int* __restrict__ cnt) {
+template <typename S, typename C, int TW>
+__global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
+                                                          int64_t k, const S* __restrict__ Ynode,
+                                                          const S* __restrict__ Tnode, int* __restrict__ cnt) {
+    constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
     typedef Mfma<C> M;
     typedef typename M::acc acc_t;
     __shared__ WideSmem<C> sm;
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(256, 1) void k_qt_tree_w(Geom g, int ngroups, S* __
     const int node = blockIdx.x / ngroups;
     const int grp = blockIdx.x - node * ngroups;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
-    const int64_t col = (int64_t)grp * 64 + 16 * wv + l16;
+    const int64_t col = (int64_t)grp * (16 * TW) + 16 * wv + l16;
     const bool colok = col < k;
     auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
     int cur = node * g.arity;
@@ -564,14 +567,14 @@ __global__ __launch_bounds__(256, 1) void k_qt_tree_w(Geom g, int ngroups, S* __
             const int64_t ch = i0 + t * stride;
             S* Bc = B + chain_start(g, (int)ch) * ldb;
             // stage Y_node (64 x 64, row-major) and T_node
-            S ys[16], ts[9];
+            S ys[YS], ts[TSN];
             const S* Yc = Ynode + ch * 4096;
             const S* Tc = Tnode + ch * W_TRI;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) ys[u] = Yc[(4 * u + wv) * 64 + lane];
+            for (int u = 0; u < YS; ++u) ys[u] = Yc[(TW * u + wv) * 64 + lane];
 #pragma unroll
-            for (int u = 0; u < 9; ++u) {
-                const int e = tid + 256 * u;
+            for (int u = 0; u < TSN; ++u) {
+                const int e = tid + NT * u;
                 ts[u] = (e < W_TRI) ? Tc[e] : S(0);
             }
             C x[16];
@@ -579,10 +582,10 @@ __global__ __launch_bounds__(256, 1) void k_qt_tree_w(Geom g, int ngroups, S* __
             for (int kk = 0; kk < 16; ++kk) x[kk] = colok ? (C)pub_load(Bc + xrow(kk) * ldb + col) : C(0);
             if (staged) __syncthreads();  // every wave is done with the previous step's operands
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sm.Y[4 * u + wv][lane] = (C)ys[u];
+            for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
 #pragma unroll
-            for (int u = 0; u < 9; ++u) {
-                const int e = tid + 256 * u;
+            for (int u = 0; u < TSN; ++u) {
+                const int e = tid + NT * u;
                 if (e < W_TRI) sm.T[e] = (C)ts[u];
             }
             __syncthreads();
@@ -661,10 +664,16 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     phase_begin(1 + MODE, st);
     static_assert(H == 64, "the chain kernel takes 64-row blocks");
     if constexpr (NP == 4) {
-        if (g.n == 64 && k >= 64) {
-            const int ngroups = (int)((k + 63) / 64);
+        if (g.n == 64 && k > 16) {
+            // 16 TW columns per workgroup, TW = 2 or 4 waves
+            const int tw = k <= 32 ? 2 : 4;
+            const int ngroups = (int)((k + 16 * tw - 1) / (16 * tw));
             const int64_t gw = (int64_t)groups * 8 * ngroups;
-            k_chain_apply_w<S, C, MODE><<<(int)gw, 256, 0, st>>>(g, Y, ldy, (const S*)wk.T_blk, B, ldb, k, ngroups);
+            const S* Tb = (const S*)wk.T_blk;
+            if (tw == 4)
+                k_chain_apply_w<S, C, MODE, 4><<<(int)gw, 256, 0, st>>>(g, Y, ldy, Tb, B, ldb, k, ngroups);
+            else
+                k_chain_apply_w<S, C, MODE, 2><<<(int)gw, 128, 0, st>>>(g, Y, ldy, Tb, B, ldb, k, ngroups);
             phase_end(1 + MODE, st);
             return hipGetLastError();
         }
@@ -680,17 +689,21 @@ template <typename S, typename C, int NC>
 static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ldb, int64_t k, hipStream_t st) {
     if (g.levels == 0) return hipSuccess;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
-    const bool wide = NP == 4 && g.n == 64 && k >= 64;
-    const int ntiles = wide ? (int)((k + 63) / 64) : (int)((k + 15) / 16);  // column groups of the launch
+    const bool wide = NP == 4 && g.n == 64 && k > 16;
+    const int tw = k <= 32 ? 2 : 4;  // waves (16-column tiles) per workgroup of the wide kernel
+    const int ntiles = wide ? (int)((k + 16 * tw - 1) / (16 * tw)) : (int)((k + 15) / 16);  // column groups
     const int64_t nodes = (g.W + g.arity - 1) / g.arity;
     int* cnt = nullptr;
     const int64_t ncnt = (int64_t)g.W * (g.levels > 1 ? g.levels - 1 : 1) * ntiles;
     hipError_t e = hipMallocAsync((void**)&cnt, (size_t)ncnt * sizeof(int), st);
     if (e != hipSuccess) return e;
     k_apply_zero<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(cnt, ncnt);
-    if (wide)
-        k_qt_tree_w<S, C><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
-                                                                     (const S*)wk.Tnode, cnt);
+    const S *Yn = (const S*)wk.Ynode, *Tn = (const S*)wk.Tnode;
+    const unsigned gridt = (unsigned)(nodes * ntiles);
+    if (wide && tw == 4)
+        k_qt_tree_w<S, C, 4><<<gridt, 256, 0, st>>>(g, ntiles, B, ldb, k, Yn, Tn, cnt);
+    else if (wide)
+        k_qt_tree_w<S, C, 2><<<gridt, 128, 0, st>>>(g, ntiles, B, ldb, k, Yn, Tn, cnt);
     else
         k_qt_tree64<S, C, NP><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
                                                                            (const S*)wk.Tnode, cnt);
