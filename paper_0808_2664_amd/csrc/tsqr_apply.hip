@@ -640,6 +640,110 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
     }
 }
 
+// One tree level of Q or the explicit Q for n = 64 with 16 TW columns per
+// workgroup, as k_node_apply64 (the node's steps, last child first), each
+// wave owning a 16-column tile over all 64 slab rows.
+template <typename S, typename C, int MODE, int TW>
+__global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, int ngroups, S* __restrict__ B,
+                                                             int64_t ldb, int64_t k, const S* __restrict__ Ynode,
+                                                             const S* __restrict__ Tnode) {
+    constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    __shared__ WideSmem<C> sm;
+    const int node = blockIdx.x / ngroups;
+    const int grp = blockIdx.x - node * ngroups;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)grp * (16 * TW) + 16 * wv + l16;
+    const bool colok = col < k;
+    auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
+    const int64_t stride = ipow(g.arity, lev - 1);
+    const int64_t i0 = (int64_t)node * g.arity * stride;
+    int nch = (int)((g.W - i0 + stride - 1) / stride);
+    if (nch > g.arity) nch = g.arity;
+    if (nch <= 1) return;
+    const int64_t sa = chain_start(g, (int)i0);
+    acc_t sl[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sl[p][i] = colok ? (C)B[(sa + 16 * p + M::orow(l4, i)) * ldb + col] : C(0);
+    bool staged = false;
+    for (int t = nch - 1; t >= 1; --t) {
+        const int64_t ch = i0 + t * stride;
+        S* Bc = B + chain_start(g, (int)ch) * ldb;
+        S ys[YS], ts[TSN];
+        const S* Yc = Ynode + ch * 4096;
+        const S* Tc = Tnode + ch * W_TRI;
+#pragma unroll
+        for (int u = 0; u < YS; ++u) ys[u] = Yc[(TW * u + wv) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < TSN; ++u) {
+            const int e = tid + NT * u;
+            ts[u] = (e < W_TRI) ? Tc[e] : S(0);
+        }
+        C x[16];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) x[kk] = (MODE != MODE_FORMQ && colok) ? (C)Bc[xrow(kk) * ldb + col] : C(0);
+        if (staged) __syncthreads();  // every wave is done with the previous step's operands
+#pragma unroll
+        for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
+#pragma unroll
+        for (int u = 0; u < TSN; ++u) {
+            const int e = tid + NT * u;
+            if (e < W_TRI) sm.T[e] = (C)ts[u];
+        }
+        __syncthreads();
+        staged = true;
+        // W = S + Y^T X (X = 0 for the explicit Q);  W' = T W (negated);  S -= W';  X -= Y W'
+        acc_t w[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            w[p] = sl[p];
+            if (MODE != MODE_FORMQ) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+            }
+        }
+        acc_t nw[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            nw[p] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int q = p; q < 4; ++q)
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    const int ti = 16 * q + M::orow(l4, kc);
+                    const int tj = 16 * p + l16;
+                    const C a = (tj <= ti) ? wide_t(sm, tj, ti) : C(0);
+                    nw[p] = M::mma(-a, w[q][kc], nw[p]);
+                }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+        }
+        if (colok) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = (S)x[kk];
+        }
+    }
+    if (colok) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) B[(sa + 16 * p + M::orow(l4, i)) * ldb + col] = (S)sl[p][i];
+    }
+}
+
 __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -768,6 +872,19 @@ static hipError_t node_apply_launch(const Geom& g, int lev, const Work& wk, S* B
     const int64_t grid = nodes * ntiles;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
+    if constexpr (NP == 4) {
+        if (g.n == 64 && k > 16) {
+            const int tw = k <= 32 ? 2 : 4;
+            const int ngroups = (int)((k + 16 * tw - 1) / (16 * tw));
+            const unsigned gw = (unsigned)(nodes * ngroups);
+            const S *Yn = (const S*)wk.Ynode, *Tn = (const S*)wk.Tnode;
+            if (tw == 4)
+                k_node_apply_w<S, C, MODE, 4><<<gw, 256, 0, st>>>(g, lev, ngroups, B, ldb, k, Yn, Tn);
+            else
+                k_node_apply_w<S, C, MODE, 2><<<gw, 128, 0, st>>>(g, lev, ngroups, B, ldb, k, Yn, Tn);
+            return hipGetLastError();
+        }
+    }
     k_node_apply64<S, C, NP, MODE><<<(int)grid, 256, 0, st>>>(g, lev, ntiles, B, ldb, k, (const S*)wk.Ynode,
                                                               (const S*)wk.Tnode);
     return hipGetLastError();
