@@ -88,8 +88,10 @@ typedef struct tsqr_opts {
  *   like LAPACK xGEQRF); the implicit Q borrows A, so A must stay alive and
  *   unmodified until tsqr_qtree_destroy.
  *   R: device n x n (ldr >= n) receives R (upper triangle; zeros below), or
- *   NULL.  q_out: receives the implicit Q, or NULL (then the tree workspace
- *   is released at the end of the stream work).
+ *   NULL.  q_out: receives the implicit Q, or NULL: then only R and the leaf
+ *   reflectors are produced (the block T factors, tau and the tree's
+ *   reflectors are not formed) and the workspace is released at the end of
+ *   the stream work.
  *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 R, 7 ldr,
  *   8 opts, 9 q_out. */
 int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,

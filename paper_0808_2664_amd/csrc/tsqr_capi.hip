@@ -145,7 +145,8 @@ static int check_dtype(int dtype) { return dtype == TSQR_F32 || dtype == TSQR_F6
 // TSQR of a device matrix into a fresh handle (shared by tsqr_factor and the
 // CAQR panels).  R: optional; r_upper_only keeps what is below R's diagonal.
 static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
-                       bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st) {
+                       bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st,
+                       bool want_q = true) {
     Geom g;
     int rc = tsqr::make_geom(m, n, opts, &g);
     if (rc != 0) return rc;
@@ -166,7 +167,7 @@ static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, vo
         return hip_fail(e);
     }
     tsqr::work_carve(&q->wk, g, f64);
-    e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, !r_upper_only, st);
+    e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, !r_upper_only, want_q, st);
     if (e != hipSuccess) {
         (void)hipFreeAsync(q->wk.base, st);
         delete q;
@@ -199,7 +200,7 @@ int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, 
     if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
     if (!R && !q_out) return -9;
     tsqr_qtree_s* q = nullptr;
-    int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream);
+    int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream, q_out != nullptr);
     if (rc != 0) return rc == -1 ? -2 : rc;
     if (q_out) *q_out = q;
     else destroy_impl(q);

@@ -85,8 +85,10 @@ inline void phase_end(int p, hipStream_t st) {
 // Launchers (defined in the .hip files).  Return a hipError_t.
 // TSQR of A into the reflectors (in A), the tree of Q factors (wk) and R
 // (row-major, ldr; zeros below the diagonal when zero_lower; R may be null).
+// want_q = false: only R and the leaf reflectors are produced (no implicit Q
+// is kept, so tau, T and the tree's reflectors are not formed or stored).
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
-                         bool zero_lower, hipStream_t st);
+                         bool zero_lower, bool want_q, hipStream_t st);
 // Host-side geometry and workspace layout (tsqr_capi.hip).
 struct GeomOpts {
     int block_rows = 0, chains = 0, arity = 0, flags = 0;

@@ -21,13 +21,13 @@ struct WaveOcc {
 
 // PIPE: the panel-pipelined binary tree; launched cooperatively, so that
 // every wave is resident and a node's wave may wait for its children.
-template <typename T, int NP, int SG, bool PIPE>
+template <typename T, int NP, int SG, bool PIPE, bool WQ>
 __global__ __launch_bounds__(64, WaveOcc<T>::value) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
                                                      T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                                      T* __restrict__ Ynode, T* __restrict__ Tnode,
                                                      T* __restrict__ tau_node, TreeArgs ta) {
     __shared__ WSmem<T, NP> sm;
-    wave_tsqr<T, NP, SG, PIPE>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
+    wave_tsqr<T, NP, SG, PIPE, WQ>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
 }
 
 __global__ void k_zero_i32(int* __restrict__ p, int64_t count) {
@@ -58,8 +58,8 @@ int wave_default_h(int NC) {
     return 64;
 }
 
-// Workgroups of k_wave_tsqr<T, NP, SG, true> the device keeps resident at once.
-template <typename T, int NP, int SG>
+// Workgroups of k_wave_tsqr<T, NP, SG, true, WQ> the device keeps resident at once.
+template <typename T, int NP, int SG, bool WQ>
 static int64_t pipe_capacity() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -68,7 +68,7 @@ static int64_t pipe_capacity() {
     if (dev < 0 || dev >= 64) return 0;
     if (!done[dev]) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true>, 64, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true, WQ>, 64, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
             per_cu = 0;
@@ -79,46 +79,51 @@ static int64_t pipe_capacity() {
     return cap[dev];
 }
 
-template <typename T, int NP, int SG>
+template <typename T, int NP, int SG, bool WQ>
 static hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
     T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
     T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
-    const bool pipe = g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG>();
+    const bool pipe = g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ>();
     if (pipe) {
         Geom gg = g;
         TreeArgs tt = ta;
         void* args[] = {&gg, &A, &lda, &tau_blk, &T_blk, &Rbuf, &Ynode, &Tnode, &tau_node, &tt};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true>, dim3(g.W), dim3(64),
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true, WQ>, dim3(g.W), dim3(64),
                                                   args, 0, st);
         if (e == hipSuccess) return hipSuccess;
         (void)hipGetLastError();  // not co-resident after all: reduce level by level
     }
-    k_wave_tsqr<T, NP, SG, false><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
+    k_wave_tsqr<T, NP, SG, false, WQ><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool WQ>
 static hipError_t factor_t(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
     const int NP = g.NC <= 16 ? 1 : g.NC / 16;
     const int SG = g.h / 16;
     if (SG != 4) return hipErrorInvalidValue;
     switch (NP) {
-        case 4: return launch_wave<T, 4, 4>(g, A, lda, wk, ta, st);
-        case 2: return launch_wave<T, 2, 4>(g, A, lda, wk, ta, st);
-        case 1: return launch_wave<T, 1, 4>(g, A, lda, wk, ta, st);
+        case 4: return launch_wave<T, 4, 4, WQ>(g, A, lda, wk, ta, st);
+        case 2: return launch_wave<T, 2, 4, WQ>(g, A, lda, wk, ta, st);
+        case 1: return launch_wave<T, 1, 4, WQ>(g, A, lda, wk, ta, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
-                         bool zero_lower, hipStream_t st) {
+                         bool zero_lower, bool want_q, hipStream_t st) {
     const int64_t ncnt = (int64_t)g.W * (g.levels + 1);
     k_zero_i32<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(wk.cnt, ncnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     TreeArgs ta{wk.cnt, R, ldr, zero_lower ? 1 : 0};
     phase_begin(0, st);
-    e = f64 ? factor_t<double>(g, (double*)A, lda, wk, ta, st) : factor_t<float>(g, (float*)A, lda, wk, ta, st);
+    if (want_q)
+        e = f64 ? factor_t<double, true>(g, (double*)A, lda, wk, ta, st)
+                : factor_t<float, true>(g, (float*)A, lda, wk, ta, st);
+    else
+        e = f64 ? factor_t<double, false>(g, (double*)A, lda, wk, ta, st)
+                : factor_t<float, false>(g, (float*)A, lda, wk, ta, st);
     phase_end(0, st);
     return e;
 }

@@ -206,8 +206,11 @@ struct NoHook {
 };
 
 // pre(p) runs before panel p and post(p) once panel p's rows of R are final
-// (its sweep and its update of the trailing columns are done).
-template <typename T, int NP, int SG, int MODE, typename Emit, typename Pre = NoHook, typename Post = NoHook>
+// (its sweep and its update of the trailing columns are done).  WQ = false:
+// only R and the reflectors are wanted (no Q is kept), so tau and T are
+// neither stored nor, above the panels' diagonal blocks, formed.
+template <typename T, int NP, int SG, int MODE, bool WQ = true, typename Emit, typename Pre = NoHook,
+          typename Post = NoHook>
 __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, const int n_, T* __restrict__ Tout,
                                            T* __restrict__ tauout, Emit&& emit, Pre&& pre = Pre{},
                                            Post&& post = Post{}) {
@@ -319,7 +322,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                     x[s][i][p] *= sc_lane;
             }
         });
-        if (l4 == 0 && c < n) tauout[c] = tau_lane;
+        if (WQ && l4 == 0 && c < n) tauout[c] = tau_lane;
 
         // diagonal T block in the MFMA D layout; to global
         wave_sync();
@@ -330,7 +333,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = c0 + M::orow(l4, r);
-            if (i <= c && c < n) Tout[tpi(i, c)] = tpp[r];
+            if (WQ && i <= c && c < n) Tout[tpi(i, c)] = tpp[r];
         }
         if constexpr (p + 1 < NP) {
             {
@@ -441,7 +444,7 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
         });
     }
 
-    if constexpr (NP == 1) {
+    if constexpr (NP == 1 || !WQ) {
         emit();
     } else {
         // ------------------------------------------------------ T blocks above the diagonal
@@ -693,7 +696,7 @@ __device__ __forceinline__ int producer_level(int W, int l, int idx) {
     return l;
 }
 
-template <typename T, int NP>
+template <typename T, int NP, bool WQ>
 __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ Rbuf,
                                                T* __restrict__ Ynode, T* __restrict__ Tnode,
                                                T* __restrict__ tau_node, const TreeArgs& ta) {
@@ -757,12 +760,14 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
         pub_wait();
         if (lane == 0) pub_flag(prog + lev * W + i0, p + 1);
     };
-    auto emit = [&]() { wstore<T, NP, NP>(x, Ynode + (int64_t)c * nn, n, 0, n, n); };
-    wave_block<T, NP, NP, 2>(x, sm, n, Tnode + (int64_t)c * tri, tau_node + (int64_t)c * n, emit, pre, post);
+    auto emit = [&]() {
+        if constexpr (WQ) wstore<T, NP, NP>(x, Ynode + (int64_t)c * nn, n, 0, n, n);
+    };
+    wave_block<T, NP, NP, 2, WQ>(x, sm, n, Tnode + (int64_t)c * tri, tau_node + (int64_t)c * n, emit, pre, post);
     if (lev == g.levels && ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
 }
 
-template <typename T, int NP, int SG, bool PIPE = false>
+template <typename T, int NP, int SG, bool PIPE = false, bool WQ = true>
 __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ A, int64_t lda,
                                           T* __restrict__ tau_blk, T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                           T* __restrict__ Ynode, T* __restrict__ Tnode, T* __restrict__ tau_node,
@@ -794,15 +799,15 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
                 }
             };
             if (b == 0)
-                wave_block<T, NP, SG, 0>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+                wave_block<T, NP, SG, 0, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
             else
-                wave_block<T, NP, SG, 1>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+                wave_block<T, NP, SG, 1, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
         }
     }
     // ---- the tree
     if constexpr (PIPE) {
         if (g.W > 1) {
-            wave_tree_pipe<T, NP>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
+            wave_tree_pipe<T, NP, WQ>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
             return;
         }
     }
@@ -844,8 +849,10 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
             } else {
                 tile_of_packed<T, NP, true>(xc, Rbuf + ch * rs, n);
             }
-            auto emit = [&]() { wstore<T, NP, NP>(xc, Ynode + ch * nn, n, 0, n, n); };
-            wave_block<T, NP, NP, 2>(xc, sm, n, Tnode + ch * tri, tau_node + ch * n, emit);
+            auto emit = [&]() {
+                if constexpr (WQ) wstore<T, NP, NP>(xc, Ynode + ch * nn, n, 0, n, n);
+            };
+            wave_block<T, NP, NP, 2, WQ>(xc, sm, n, Tnode + ch * tri, tau_node + ch * n, emit);
         }
         cur = i0;
     }

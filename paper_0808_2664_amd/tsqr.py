@@ -115,11 +115,12 @@ class QTree:
 
 
 def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0,
-           levelwise: bool = False):
+           levelwise: bool = False, want_q: bool = True):
     """TSQR of A (m x n, m >= n, n <= 64), IN PLACE: A is overwritten by the
     leaf reflectors.  Returns (R, QTree); diag(R) carries the Householder
     signs (see sign_normalize).  levelwise: reduce the tree node by node
-    (TSQR_FLAG_TREE_LEVELWISE) instead of panel-pipelined; same result."""
+    (TSQR_FLAG_TREE_LEVELWISE) instead of panel-pipelined; same result.
+    want_q=False: R only (no implicit Q is formed); returns (R, None)."""
     lib = _lib.load()
     m, n = A.shape
     if R is None:
@@ -127,9 +128,9 @@ def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=
     h = ctypes.c_void_p()
     flags = _lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0
     rc = lib.tsqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(R), _ld(R),
-                         _opts(block_rows, chains, arity, flags), ctypes.byref(h), _stream(A))
+                         _opts(block_rows, chains, arity, flags), ctypes.byref(h) if want_q else None, _stream(A))
     _lib.check("tsqr_factor", rc)
-    return R, QTree(h, A, m, n)
+    return R, (QTree(h, A, m, n) if want_q else None)
 
 
 def sign_normalize(Q: torch.Tensor | None, R: torch.Tensor):

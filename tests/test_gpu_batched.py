@@ -55,12 +55,17 @@ def test_batched_mixed_f64_matches_oracle_and_single_calls():
         assert e <= 1e-11, (i, shapes[i], e)
     _note("  worst R error %.2e" % worst)
     # bitwise equal to single-matrix factorisations with the same tree shape
+    # (R only, as the batch), and equal to rounding to the Q-keeping ones
     for i in [0, 5, 17, 60, 61, 62, 63, 64, 65]:
         A1 = torch.from_numpy(As[i]).cuda()
-        R1, qt = tq.factor(A1, chains=opts[i][0], arity=opts[i][1])
+        R1, none = tq.factor(A1, chains=opts[i][0], arity=opts[i][1], want_q=False)
+        A2 = torch.from_numpy(As[i]).cuda()
+        R2, qt = tq.factor(A2, chains=opts[i][0], arity=opts[i][1])
         torch.cuda.synchronize()
+        assert none is None
         assert torch.equal(R1, Rs[i]), i
         assert torch.equal(A1, dev[i]), i       # the same reflectors in place
+        assert torch.linalg.norm(R2 - R1).item() <= 1e-14 * torch.linalg.norm(R1).item(), i
         qt.close()
     plan.close()
 
