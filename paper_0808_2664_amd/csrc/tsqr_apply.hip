@@ -439,6 +439,14 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
                 for (int i = 0; i < 4; ++i) x[4 * p + i] = sl[p][i];
         }
+        // the next block's loads fly during the whole block where the
+        // register file has room for them (one wave per SIMD, four waves),
+        // else during X -= Y W' only
+        constexpr bool early = TW == 4 && (sizeof(C) == 8 || MODE == MODE_QT);
+        if (early && more) {
+            stage_load(bi + 1);
+            x_load(bi + 1);
+        }
         // W = V^T [S; X]
         acc_t w[4];
         const bool xzero = (MODE == MODE_FORMQ) && !top;
@@ -473,8 +481,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
             for (int p = 0; p < 4; ++p) sl[p] += nw[p];
         }
-        // the next block's loads fly during X -= Y W'
-        if (more) {
+        if (!early && more) {
             stage_load(bi + 1);
             x_load(bi + 1);
         }
