@@ -220,7 +220,7 @@ def main():
         cpu = cpu_baseline(min(a.cpu_rows, m), n, k)
     extras = {}
     if not a.no_extras:
-        for name, fn in (("batched", bench_batched), ("caqr", bench_caqr), ("fwd_bwd", bench_fwd_bwd)):
+        for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn(tq, torch, np)
             torch.cuda.empty_cache()
@@ -403,8 +403,10 @@ def bench_fwd_bwd(tq, torch, np):
         torch.autograd.backward((Q, R), (dQ, dR))
     for f in (fwd, fwd_bwd):
         f()
-    t_f = _ev_ms(torch, fwd, 5)
-    t_fb = _ev_ms(torch, fwd_bwd, 5)
+    # small problem: host launch gaps are a visible part of each call, so
+    # take the median of many calls
+    t_f = _ev_ms(torch, fwd, 21)
+    t_fb = _ev_ms(torch, fwd_bwd, 21)
     m, n = A.shape
     # HBM words: forward reads A, writes Y, reads Y, writes Q; backward reads Q, R, dQ, writes dA
     fb_bytes = 8.0 * m * n * (4 + 3)
