@@ -54,10 +54,11 @@ def _load():
         lib.oracle_apply_q.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_form_q.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_qr_adjoint.argtypes = [i64, i64, dp, dp, dp, dp, dp]
+        lib.oracle_lstsq.argtypes = [i64, i64, i64, dp, dp, dp, dp]
         lib.oracle_psum.argtypes = [dp, i64]
         lib.oracle_psum.restype = ctypes.c_double
         for f in ("oracle_geqrf", "oracle_apply_qt", "oracle_apply_q",
-                  "oracle_form_q", "oracle_qr_adjoint"):
+                  "oracle_form_q", "oracle_qr_adjoint", "oracle_lstsq"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -153,6 +154,22 @@ def qr_adjoint(Q, R, dQ, dR):
     _check(_load().oracle_qr_adjoint(m, n, _p(Q), _p(R), _p(dQ), _p(dR), _p(dA)),
            "oracle_qr_adjoint")
     return dA
+
+
+def lstsq(A, B):
+    """Least squares min ||A X - B|| column by column (A full column rank):
+    returns (X, rnorm), X n x k, rnorm the k residual norms.  A 1-D B gives
+    a 1-D X and a scalar rnorm."""
+    A, B = _f64(A), _f64(B)
+    m, n = A.shape
+    vec = B.ndim == 1
+    Bc = B.reshape(m, 1) if vec else B
+    k = Bc.shape[1]
+    X = np.empty((n, k))
+    rn = np.empty(k)
+    _check(_load().oracle_lstsq(m, n, k, _p(A), _p(np.ascontiguousarray(Bc)), _p(X), _p(rn)),
+           "oracle_lstsq")
+    return (X.ravel(), float(rn[0])) if vec else (X, rn)
 
 
 # ---- evaluation helpers (norms of the checks; no factorisation arithmetic) ----

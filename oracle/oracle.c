@@ -294,5 +294,64 @@ int oracle_qr_adjoint(int64_t m, int64_t n, const double *Q, const double *R,
     return 0;
 }
 
+/*
+ * Linear least squares: for each column b of B (m x k), the x minimising
+ * ||A x - b||_2, A m x n of full column rank (m >= n).  The QR factorisation
+ * is the paper's tool for this problem (Sec. 1, the remark on solving a least
+ * squares problem with TSQR): with A = Q R and c = Q^T b (full m x m Q),
+ * x solves R x = c(0:n) and the residual norm is ||c(n:m)||_2, since Q
+ * preserves norms.  Steps: Householder QR (oracle_geqrf), Q^T B
+ * (oracle_apply_qt), back substitution row by row from the last, and a
+ * pairwise sum of the squares of the trailing m - n entries per column.
+ * Inputs row-major: A m x n, B m x k.  Outputs: X n x k (row-major), rnorm
+ * k entries.  Returns 0, -1 for bad sizes, -2 on allocation failure.
+ */
+int oracle_lstsq(int64_t m, int64_t n, int64_t k, const double *A, const double *B,
+                 double *X, double *rnorm)
+{
+    if (m < 0 || n < 0 || k < 0 || m < n)
+        return -1;
+    double *yr = (double *)malloc((size_t)(m * n > 0 ? m * n : 1) * sizeof(double));
+    double *tau = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *c = (double *)malloc((size_t)(m * k > 0 ? m * k : 1) * sizeof(double));
+    double *sq = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    if (!yr || !tau || !c || !sq) {
+        free(yr);
+        free(tau);
+        free(c);
+        free(sq);
+        return -2;
+    }
+    memcpy(yr, A, (size_t)(m * n) * sizeof(double));
+    memcpy(c, B, (size_t)(m * k) * sizeof(double));
+    int rc = oracle_geqrf(m, n, yr, tau);
+    if (rc == 0)
+        rc = oracle_apply_qt(m, n, k, yr, tau, c);
+    if (rc != 0) {
+        free(yr);
+        free(tau);
+        free(c);
+        free(sq);
+        return rc == -1 ? -1 : -2;
+    }
+    for (int64_t col = 0; col < k; ++col) {
+        /* R x = c(0:n): R is the upper triangle of yr */
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double acc = c[i * k + col];
+            for (int64_t l = i + 1; l < n; ++l)
+                acc -= yr[i * n + l] * X[l * k + col];
+            X[i * k + col] = acc / yr[i * n + i];
+        }
+        for (int64_t i = n; i < m; ++i)
+            sq[i - n] = c[i * k + col] * c[i * k + col];
+        rnorm[col] = sqrt(psum(sq, m - n));
+    }
+    free(yr);
+    free(tau);
+    free(c);
+    free(sq);
+    return 0;
+}
+
 /* Exposed for the tests: pairwise sum of n doubles. */
 double oracle_psum(const double *x, int64_t n) { return psum(x, n); }

@@ -243,6 +243,51 @@ def test_least_squares_matches_lstsq():
     assert abs(np.sum(c[n:] ** 2) - res[0]) < 1e-10 * res[0]
 
 
+def test_lstsq_hand_3x2():
+    # x = (4/9, 1/9) and residual norm 1/3, worked by hand (golden fixture)
+    g = _load("householder_3x2.json")
+    A = _fmat(g["A"])
+    b = np.array([_frac(v) for v in g["b"]])
+    x, rn = oracle.lstsq(A, b)
+    np.testing.assert_allclose(x, [_frac(v) for v in g["lstsq_x"]], rtol=0, atol=1e-15)
+    assert abs(rn - _frac(g["lstsq_residual_norm"])) < 1e-15
+    # two right-hand sides at once: b and 3b - A e_0 (solution 3x - e_0, residual 3 * 1/3)
+    B = np.stack([b, 3 * b - A[:, 0]], axis=1)
+    X, rns = oracle.lstsq(A, B)
+    np.testing.assert_allclose(X[:, 0], x, atol=1e-15)
+    np.testing.assert_allclose(X[:, 1], [3 * 4 / 9 - 1, 3 * 1 / 9], atol=1e-15)
+    np.testing.assert_allclose(rns, [1 / 3, 1.0], atol=1e-15)
+
+
+def test_lstsq_consistent_and_square_systems():
+    # B = A X0 has the exact solution X0 and zero residual; a square A has no
+    # residual rows at all
+    A = workloads.gaussian(300, 12, 81)
+    X0 = workloads.gaussian(12, 5, 82)
+    X, rn = oracle.lstsq(A, A @ X0)
+    np.testing.assert_allclose(X, X0, rtol=0, atol=1e-12)
+    assert np.all(rn < 1e-12)
+    S = workloads.gaussian(10, 10, 83) + 10 * np.eye(10)
+    Bs = workloads.gaussian(10, 3, 84)
+    Xs, rs = oracle.lstsq(S, Bs)
+    np.testing.assert_allclose(Xs, np.linalg.solve(S, Bs), rtol=1e-12, atol=1e-13)
+    assert np.all(rs == 0.0)
+
+
+@pytest.mark.parametrize("m,n,k", [(500, 9, 4), (2000, 64, 3), (70, 64, 1)])
+def test_lstsq_against_library_and_normal_equations(m, n, k):
+    A = workloads.gaussian(m, n, 91 + n)
+    B = workloads.gaussian(m, k, 92 + n)
+    X, rn = oracle.lstsq(A, B)
+    Xr, res, _, _ = np.linalg.lstsq(A, B, rcond=None)
+    np.testing.assert_allclose(X, Xr, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(rn ** 2, res, rtol=1e-10)
+    # the residual is orthogonal to range(A): A^T (A X - B) = 0
+    Rs = A @ X - B
+    assert np.linalg.norm(A.T @ Rs) <= 1e-12 * np.linalg.norm(A) * np.linalg.norm(Rs)
+    np.testing.assert_allclose(np.linalg.norm(Rs, axis=0), rn, rtol=1e-12)
+
+
 def test_pairwise_sum():
     x = np.arange(1, 1001, dtype=np.float64)
     assert oracle.psum(x) == 500500.0
