@@ -52,7 +52,7 @@ def parse():
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, CAQR and forward+backward measurements")
-    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd"), default=None,
+    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "lstsq"), default=None,
                    help="run only this measurement and print its JSON (for profiling it)")
     return p.parse_args()
 
@@ -121,7 +121,7 @@ def main():
     import torch
     if a.extra:
         import paper_0808_2664_amd as tq_x
-        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd}[a.extra]
+        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "lstsq": bench_lstsq}[a.extra]
         print(json.dumps({a.extra: fn(tq_x, torch, np)}), flush=True)
         return
 
@@ -220,7 +220,8 @@ def main():
         cpu = cpu_baseline(min(a.cpu_rows, m), n, k)
     extras = {}
     if not a.no_extras:
-        for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd)):
+        for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd),
+                         ("lstsq", bench_lstsq)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn(tq, torch, np)
             torch.cuda.empty_cache()
@@ -413,6 +414,55 @@ def bench_fwd_bwd(tq, torch, np):
     return {"workload": "TSQR forward (factor + Q) and backward (QR adjoint), 262144 x 32 FP64",
             "fwd_ms": round(t_f, 4), "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3),
             "fwd_bwd_alg_gbs": round(fb_bytes / (t_fb / 1e3) / 1e9, 1)}
+
+
+def bench_lstsq(tq, torch, np):
+    """Least squares through TSQR (factor, Q^T B, back substitution, residual
+    norms) on the step's inputs: 2^20 x 64 FP64 (cond 1e8, seeds 2, 3) with
+    32 right-hand sides (seed 4); the library call alone, on buffers
+    refilled from pristine copies before each call."""
+    import ctypes
+
+    import workloads
+    from paper_0808_2664_amd import _lib
+    A_np, B_np = workloads.cfg2()
+    A0 = torch.from_numpy(A_np).cuda()
+    B0 = torch.from_numpy(B_np).cuda()
+    del A_np, B_np
+    m, n = A0.shape
+    k = B0.shape[1]
+    W, Bw = A0.clone(), B0.clone()
+    rn = torch.empty(k, dtype=torch.float64, device="cuda")
+    lib = _lib.load()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        rc = lib.tsqr_lstsq(_lib.TSQR_F64, m, n, ctypes.c_void_p(W.data_ptr()), n, k,
+                            ctypes.c_void_p(Bw.data_ptr()), k, ctypes.c_void_p(rn.data_ptr()), None, st)
+        _lib.check("tsqr_lstsq", rc)
+    ts = []
+    for it in range(13):
+        W.copy_(A0)
+        Bw.copy_(B0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        torch.cuda.synchronize()
+        if it >= 3:
+            ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    # nominal counts: factor 2mn^2 - 2n^3/3, Q^T B 4mnk - 2n^2k, solve n^2 k
+    fl = 2.0 * m * n * n - 2.0 * n ** 3 / 3 + 4.0 * m * n * k - 2.0 * n * n * k + n * n * k
+    # words: read A, write the reflectors, read them again, read and write B
+    by = 8.0 * (3 * m * n + 2 * m * k)
+    # residual check in FP64 on the device: ||A X - B|| per column against rnorm
+    X = Bw[:n]
+    rr = torch.linalg.norm(A0 @ X - B0, dim=0)
+    return {"workload": "least squares, 1048576 x 64 FP64 (cond 1e8), 32 right-hand sides",
+            "ms": round(ms, 4), "gflops": round(fl / (ms / 1e3) / 1e9, 1),
+            "alg_gbs": round(by / (ms / 1e3) / 1e9, 1),
+            "rnorm_vs_residual": float(torch.max(torch.abs(rr - rn) / rr))}
 
 
 def ctypes_ptr(event):

@@ -104,6 +104,26 @@ int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, 
  * Errors: 1 q, 2 k, 3 B, 4 ldb. */
 int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
 
+/* Linear least squares: for each of the k columns b of B, the x minimising
+ * ||A x - b||_2 (Sec. 1: the remark on least squares problems solved with the
+ * QR factorisation).  TSQR of A, then B <- Q^T B through the tree of Q
+ * factors, then back substitution R x = (Q^T b)(0:n); Q preserves norms, so
+ * the residual norm of b is the 2-norm of rows n..m-1 of Q^T b.
+ *   dtype, m, n, A, lda as for tsqr_factor (m >= n >= 1, n <= 64); A must
+ *   have full column rank (a zero diagonal entry of R gives Inf/NaN in X; it
+ *   is not detected).  A is OVERWRITTEN with the leaf reflectors.
+ *   B: device m x k (ldb >= k), OVERWRITTEN: rows 0..n-1 hold X (n x k), rows
+ *   n..m-1 the trailing rows of Q^T B (LAPACK xGELS layout).  k = 0: A is
+ *   factored (R only) and nothing else is written.
+ *   rnorm: device array of k residual norms (in dtype; sums of squares in
+ *   FP64, added in a fixed order), or NULL.
+ *   All temporaries (R, the implicit Q's workspace, partial sums) are
+ *   stream-ordered allocations released at the end of the stream work.
+ *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 k, 7 B,
+ *   8 ldb, 10 opts. */
+int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k, void* B, int64_t ldb,
+               void* rnorm, const tsqr_opts* opts, void* stream);
+
 /* B <- Q B (reverse order of tsqr_apply_qt).  Same arguments. */
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
 

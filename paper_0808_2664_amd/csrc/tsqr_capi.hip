@@ -238,6 +238,44 @@ int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
     return apply_impl(q, k, B, ldb, tsqr::MODE_QT, (hipStream_t)stream);
 }
 
+int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k, void* B, int64_t ldb, void* rnorm,
+               const tsqr_opts* opts, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (k < 0) return -6;
+    if (k > 0 && !B) return -7;
+    if (k > 0 && ldb < k) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -10;
+    if (k > ((int64_t)1 << 36)) return TSQR_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = dtype == TSQR_F64;
+    void* R = nullptr;
+    hipError_t e = hipMallocAsync(&R, (size_t)(n * n) * (f64 ? 8 : 4), st);
+    if (e != hipSuccess) return hip_fail(e);
+    tsqr_qtree_s* q = nullptr;
+    // without right-hand sides only R is needed (no implicit Q is formed)
+    int rc = factor_impl(dtype, m, n, A, lda, R, n, false, opts, &q, st, k > 0);
+    if (rc == -1) rc = -2;
+    if (rc == 0 && k > 0) {
+        rc = apply_one(q, k, B, ldb, tsqr::MODE_QT, f64, st);
+        if (rc == 0) {
+            e = tsqr::launch_trsm_upper(f64, n, R, n, B, ldb, k, st);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+        if (rc == 0 && rnorm) {
+            e = tsqr::launch_colnorm(f64, n, m, B, ldb, k, rnorm, st);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+    }
+    if (q) destroy_impl(q);
+    (void)hipFreeAsync(R, st);
+    return rc;
+}
+
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
     if (!q) return -1;
     if (k < 0) return -2;

@@ -106,6 +106,12 @@ hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const v
                         const Work& wk, void* B, int64_t ldb, int64_t k, int mode, hipStream_t st);
 hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st);
 hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+// Least squares steps after Q^T B (tsqr_lstsq.hip): X = R^{-1} B(0:n, :) in
+// place, and the 2-norms of rows [r0, m) of each of the k columns of B.
+hipError_t launch_trsm_upper(bool f64, int64_t n, const void* R, int64_t ldr, void* B, int64_t ldb, int64_t k,
+                             hipStream_t st);
+hipError_t launch_colnorm(bool f64, int64_t r0, int64_t m, const void* B, int64_t ldb, int64_t k, void* rnorm,
+                          hipStream_t st);
 hipError_t launch_backward(bool f64, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t sq,
                            const void* R, int64_t ldr, int64_t sr, const void* dQ, int64_t lddq, int64_t sdq,
                            const void* dR, int64_t lddr, int64_t sdr, void* dA, int64_t ldda, int64_t sda,

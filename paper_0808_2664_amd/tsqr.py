@@ -133,6 +133,29 @@ def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=
     return R, (QTree(h, A, m, n) if want_q else None)
 
 
+def lstsq(A: torch.Tensor, B: torch.Tensor, rnorm: bool = True, block_rows=0, chains=0, arity=0):
+    """Least squares min ||A X - B|| column by column (A m x n of full column
+    rank, m >= n, n <= 64; B m x k or a vector of m).  Returns (X, rnorm):
+    X n x k (or n), rnorm the k residual norms (or None).  A and B are not
+    modified: the library works on copies (tsqr_lstsq overwrites both)."""
+    lib = _lib.load()
+    m, n = A.shape
+    if B.dtype != A.dtype or B.device != A.device or B.size(0) != m:
+        raise ValueError("B must be an m x k (or m) tensor of A's dtype and device")
+    vec = B.dim() == 1
+    W = A.contiguous().clone()
+    Bw = (B.reshape(m, 1) if vec else B).contiguous().clone()
+    k = Bw.size(1)
+    rn = torch.empty(k, dtype=A.dtype, device=A.device) if rnorm and k > 0 else None
+    rc = lib.tsqr_lstsq(_dtype_code(A), m, n, _ptr(W), _ld(W), k, _ptr(Bw), max(k, 1),
+                        _ptr(rn) if rn is not None else None, _opts(block_rows, chains, arity), _stream(A))
+    _lib.check("tsqr_lstsq", rc)
+    X = Bw[:n]
+    if vec:
+        return X[:, 0], (rn[0] if rn is not None else None)
+    return X, rn
+
+
 def sign_normalize(Q: torch.Tensor | None, R: torch.Tensor):
     """R <- D R, Q <- Q D with D = sign(diag R), sign(0) = +1 (in place)."""
     lib = _lib.load()

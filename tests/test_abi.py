@@ -131,3 +131,21 @@ def test_implicit_q_parameter_count():
         leaves = W * (h * n - n * (n + 1) // 2)
         steps = (W - 1) * (n * (n + 1) // 2)
         assert leaves + steps == m * n - n * (n + 1) // 2
+
+
+def test_lstsq_argument_errors_without_launch():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: every call below fails its checks first
+    f = lib.tsqr_lstsq
+    assert f(7, 100, 4, fake, 4, 2, fake, 2, None, None, None) == -1           # dtype
+    assert f(1, 3, 4, fake, 4, 2, fake, 2, None, None, None) == -2             # m < n
+    assert f(1, 100, 0, fake, 4, 2, fake, 2, None, None, None) == -3           # n
+    assert f(1, 100, 65, fake, 65, 2, fake, 2, None, None, None) == _lib.TSQR_ERR_UNSUPPORTED
+    assert f(1, 100, 4, None, 4, 2, fake, 2, None, None, None) == -4           # A
+    assert f(1, 100, 4, fake, 3, 2, fake, 2, None, None, None) == -5           # lda
+    assert f(1, 100, 4, fake, 4, -1, fake, 2, None, None, None) == -6          # k
+    assert f(1, 100, 4, fake, 4, 2, None, 2, None, None, None) == -7           # B
+    assert f(1, 100, 4, fake, 4, 2, fake, 1, None, None, None) == -8           # ldb
+    bad = _lib.opts(flags=2)
+    assert f(1, 100, 4, fake, 4, 2, fake, 2, None, ctypes.byref(bad), None) == -10
