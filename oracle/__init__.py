@@ -14,6 +14,7 @@ paper it follows is stated in ``oracle.c``; the conventions are:
 * comparisons are made after the sign normalisation ``D = sign(diag R)``,
   since the factorisation is unique only up to those signs (Sec. 2.1).
 
+``cholqr`` is the CholeskyQR the paper compares TSQR with (Sec. 2.3).
 ``qr_adjoint`` is not from the paper: it is the published QR adjoint
 (Walter & Lehmann; Liao et al. "copyltu" form).
 """
@@ -55,10 +56,11 @@ def _load():
         lib.oracle_form_q.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_qr_adjoint.argtypes = [i64, i64, dp, dp, dp, dp, dp]
         lib.oracle_lstsq.argtypes = [i64, i64, i64, dp, dp, dp, dp]
+        lib.oracle_cholqr.argtypes = [i64, i64, dp, dp, dp, ctypes.c_int]
         lib.oracle_psum.argtypes = [dp, i64]
         lib.oracle_psum.restype = ctypes.c_double
         for f in ("oracle_geqrf", "oracle_apply_qt", "oracle_apply_q",
-                  "oracle_form_q", "oracle_qr_adjoint", "oracle_lstsq"):
+                  "oracle_form_q", "oracle_qr_adjoint", "oracle_lstsq", "oracle_cholqr"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -170,6 +172,21 @@ def lstsq(A, B):
     _check(_load().oracle_lstsq(m, n, k, _p(A), _p(np.ascontiguousarray(Bc)), _p(X), _p(rn)),
            "oracle_lstsq")
     return (X.ravel(), float(rn[0])) if vec else (X, rn)
+
+
+def cholqr(A, passes: int = 1):
+    """CholeskyQR (passes = 1) or CholeskyQR2 (passes = 2): returns (Q, R),
+    diag(R) > 0.  Raises FloatingPointError if a Cholesky pivot is not
+    positive (A^T A not numerically positive definite)."""
+    A = _f64(A)
+    m, n = A.shape
+    Q = np.empty((m, n))
+    R = np.empty((n, n))
+    rc = _load().oracle_cholqr(m, n, _p(A), _p(Q), _p(R), int(passes))
+    if rc == -3:
+        raise FloatingPointError("Cholesky pivot not positive")
+    _check(rc, "oracle_cholqr")
+    return Q, R
 
 
 # ---- evaluation helpers (norms of the checks; no factorisation arithmetic) ----

@@ -353,5 +353,105 @@ int oracle_lstsq(int64_t m, int64_t n, int64_t k, const double *A, const double 
     return 0;
 }
 
+/*
+ * CholeskyQR, the fast but conditionally stable alternative the paper
+ * compares TSQR with (Sec. 2.3 and its sequential cost table): G = A^T A,
+ * R = the upper triangular Cholesky factor of G (R^T R = G, positive
+ * diagonal), Q = A R^{-1}.  With passes = 2 (CholeskyQR2) the same steps are
+ * applied to Q, giving Q2 and R2, and R = R2 R1.
+ * Textbook steps: G entries by pairwise sums over the m rows; Cholesky
+ * R_jj = sqrt(G_jj - sum_{k<j} R_kj^2), R_jc = (G_jc - sum_{k<j} R_kj R_kc) / R_jj;
+ * each row q of Q from q R = a by forward substitution.
+ * Inputs row-major: A m x n.  Outputs: Q m x n, R n x n (zeros below the
+ * diagonal).  Returns 0, -1 for bad sizes, -2 on allocation failure, -3 if a
+ * Cholesky pivot is not positive (G not numerically positive definite).
+ */
+static int cholqr_pass(int64_t m, int64_t n, const double *A, double *Q, double *R)
+{
+    double *ac = to_cm(m, n, A);
+    scratch_t s = {0, 0};
+    double *G = (double *)malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(double));
+    if (!ac || !G || scratch_reserve(&s, m > 0 ? m : 1) != 0) {
+        free(ac);
+        free(G);
+        free(s.p);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i; j < n; ++j)
+            G[i * n + j] = pdot(&s, ac + i * m, ac + j * m, m);
+    free(ac);
+    free(s.p);
+    int rc = 0;
+    memset(R, 0, (size_t)(n * n) * sizeof(double));
+    for (int64_t j = 0; j < n && rc == 0; ++j) {
+        double d = G[j * n + j];
+        for (int64_t k = 0; k < j; ++k)
+            d -= R[k * n + j] * R[k * n + j];
+        if (!(d > 0.0)) {
+            rc = -3;
+            break;
+        }
+        R[j * n + j] = sqrt(d);
+        for (int64_t c = j + 1; c < n; ++c) {
+            double v = G[j * n + c];
+            for (int64_t k = 0; k < j; ++k)
+                v -= R[k * n + j] * R[k * n + c];
+            R[j * n + c] = v / R[j * n + j];
+        }
+    }
+    free(G);
+    if (rc != 0)
+        return rc;
+    for (int64_t r = 0; r < m; ++r) {
+        for (int64_t j = 0; j < n; ++j) {
+            double v = A[r * n + j];
+            for (int64_t k = 0; k < j; ++k)
+                v -= Q[r * n + k] * R[k * n + j];
+            Q[r * n + j] = v / R[j * n + j];
+        }
+    }
+    return 0;
+}
+
+int oracle_cholqr(int64_t m, int64_t n, const double *A, double *Q, double *R, int passes)
+{
+    if (m < 0 || n < 0 || m < n || passes < 1 || passes > 2)
+        return -1;
+    int rc = cholqr_pass(m, n, A, Q, R);
+    if (rc != 0 || passes == 1)
+        return rc;
+    double *Q1 = (double *)malloc((size_t)(m * n > 0 ? m * n : 1) * sizeof(double));
+    double *R1 = (double *)malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(double));
+    if (!Q1 || !R1) {
+        free(Q1);
+        free(R1);
+        return -2;
+    }
+    memcpy(Q1, Q, (size_t)(m * n) * sizeof(double));
+    memcpy(R1, R, (size_t)(n * n) * sizeof(double));
+    double *R2 = (double *)malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(double));
+    if (!R2) {
+        free(Q1);
+        free(R1);
+        return -2;
+    }
+    rc = cholqr_pass(m, n, Q1, Q, R2);
+    if (rc == 0) {
+        /* R = R2 R1, both upper triangular */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                double v = 0.0;
+                for (int64_t l = i; l <= j; ++l)
+                    v += R2[i * n + l] * R1[l * n + j];
+                R[i * n + j] = (j >= i) ? v : 0.0;
+            }
+    }
+    free(Q1);
+    free(R1);
+    free(R2);
+    return rc;
+}
+
 /* Exposed for the tests: pairwise sum of n doubles. */
 double oracle_psum(const double *x, int64_t n) { return psum(x, n); }

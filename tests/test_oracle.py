@@ -288,6 +288,49 @@ def test_lstsq_against_library_and_normal_equations(m, n, k):
     np.testing.assert_allclose(np.linalg.norm(Rs, axis=0), rn, rtol=1e-12)
 
 
+def test_cholqr_hand_3x2():
+    # A^T A = [[9, 9], [9, 18]]: R = [[3, 3], [0, 3]], Q = A R^-1 (golden fixture)
+    g = _load("householder_3x2.json")
+    A = _fmat(g["A"])
+    for passes in (1, 2):
+        Q, R = oracle.cholqr(A, passes)
+        np.testing.assert_allclose(R, _fmat(g["R_normalised"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(Q, _fmat(g["Q_normalised"]), rtol=0, atol=1e-15)
+
+
+def test_cholqr_closed_form_u_times_triangle():
+    # A = U T with orthonormal U and upper triangular T (positive diagonal):
+    # A^T A = T^T T, so R = T and Q = U exactly (a transposed or mis-indexed
+    # factor fails here)
+    m, n = 400, 6
+    U = np.linalg.qr(workloads.gaussian(m, n, 61))[0]
+    T = np.triu(np.arange(1, n * n + 1, dtype=np.float64).reshape(n, n) % 7 + 1)
+    for passes in (1, 2):
+        Q, R = oracle.cholqr(U @ T, passes)
+        np.testing.assert_allclose(R, T, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(Q, U, rtol=0, atol=1e-13)
+
+
+def test_cholqr_matches_householder_r_and_loses_orthogonality():
+    # R is unique with a positive diagonal (Sec. 4 Cor. 1: the Cholesky factor
+    # of A^T A), so it matches the sign-normalised Householder R on a
+    # well-conditioned input; at cond 1e7 one pass loses orthogonality
+    # (~cond^2 u) and the second pass restores it
+    A = workloads.gaussian(3000, 16, 62)
+    Q, R = oracle.cholqr(A)
+    Qh, Rh = oracle.qr(A)
+    assert oracle.rel_err(R, Rh) < 1e-13
+    assert oracle.orthogonality(Q) < 1e-13
+    B = workloads.conditioned(3000, 16, 1e7, 63, 64)
+    Q1, _ = oracle.cholqr(B, 1)
+    Q2, R2 = oracle.cholqr(B, 2)
+    assert oracle.orthogonality(Q1) > 1e-6
+    assert oracle.orthogonality(Q2) < 1e-13
+    assert oracle.residual(B, Q2, R2) < 1e-14
+    with pytest.raises(FloatingPointError):
+        oracle.cholqr(workloads.conditioned(3000, 16, 1e12, 65, 66))
+
+
 def test_pairwise_sum():
     x = np.arange(1, 1001, dtype=np.float64)
     assert oracle.psum(x) == 500500.0
