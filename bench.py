@@ -52,7 +52,7 @@ def parse():
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, CAQR and forward+backward measurements")
-    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "lstsq"), default=None,
+    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "lstsq", "cholqr"), default=None,
                    help="run only this measurement and print its JSON (for profiling it)")
     return p.parse_args()
 
@@ -121,7 +121,8 @@ def main():
     import torch
     if a.extra:
         import paper_0808_2664_amd as tq_x
-        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "lstsq": bench_lstsq}[a.extra]
+        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "lstsq": bench_lstsq,
+              "cholqr": bench_cholqr}[a.extra]
         print(json.dumps({a.extra: fn(tq_x, torch, np)}), flush=True)
         return
 
@@ -221,7 +222,7 @@ def main():
     extras = {}
     if not a.no_extras:
         for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd),
-                         ("lstsq", bench_lstsq)):
+                         ("lstsq", bench_lstsq), ("cholqr", bench_cholqr)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn(tq, torch, np)
             torch.cuda.empty_cache()
@@ -463,6 +464,63 @@ def bench_lstsq(tq, torch, np):
             "ms": round(ms, 4), "gflops": round(fl / (ms / 1e3) / 1e9, 1),
             "alg_gbs": round(by / (ms / 1e3) / 1e9, 1),
             "rnorm_vs_residual": float(torch.max(torch.abs(rr - rn) / rr))}
+
+
+def bench_cholqr(tq, torch, np):
+    """TSQR against CholeskyQR and CholeskyQR2 (the comparison of Sec. 2.3)
+    on 2^20 x 64 FP64: the step's matrix (cond 1e8, seeds 2, 3) and a
+    Gaussian one (seed 2).  TSQR = factor + form Q on a copy refilled before
+    each call; CholeskyQR reads A and writes Q.  Median of 10 calls each, with
+    the orthogonality ||Q^T Q - I||_F of the result (null where the Cholesky
+    factorisation broke down)."""
+    import workloads
+    out = {"workload": "TSQR vs CholeskyQR / CholeskyQR2, 1048576 x 64 FP64"}
+    for name, A_np in (("cond_1e8", workloads.conditioned(1 << 20, 64, 1e8, 2, 3)),
+                       ("gaussian", workloads.gaussian(1 << 20, 64, 2))):
+        A0 = torch.from_numpy(A_np).cuda()
+        del A_np
+        W = A0.clone()
+        Q = torch.empty_like(A0)
+
+        def orth(Qx):
+            if not bool(torch.isfinite(Qx).all()):
+                return None
+            G = Qx.T.contiguous() @ Qx
+            return float(torch.linalg.norm(G - torch.eye(G.shape[0], dtype=G.dtype, device=G.device)))
+
+        def timed(fn, pre=None):
+            ts = []
+            for it in range(13):
+                if pre is not None:
+                    pre()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                if it >= 3:
+                    ts.append(e0.elapsed_time(e1))
+            return sorted(ts)[len(ts) // 2]
+        box = {}
+
+        def tsqr_call():
+            _, qt = tq.factor(W)
+            qt.form_q(out=Q)
+            box["qt"] = qt
+
+        def tsqr_pre():
+            if "qt" in box:
+                box.pop("qt").close()
+            W.copy_(A0)
+        res = {"tsqr_ms": round(timed(tsqr_call, tsqr_pre), 4), "tsqr_orthogonality": orth(Q)}
+        box.pop("qt").close()
+        for passes, key in ((1, "cholqr"), (2, "cholqr2")):
+            res[key + "_ms"] = round(timed(lambda: tq.cholqr(A0, passes, out_q=Q)), 4)
+            res[key + "_orthogonality"] = orth(Q)
+        out[name] = res
+        del A0, W, Q
+        torch.cuda.empty_cache()
+    return out
 
 
 def ctypes_ptr(event):

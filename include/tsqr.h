@@ -124,6 +124,21 @@ int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
 int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k, void* B, int64_t ldb,
                void* rnorm, const tsqr_opts* opts, void* stream);
 
+/* CholeskyQR, the fast but conditionally stable algorithm the paper compares
+ * TSQR with (Sec. 2.3 and its sequential cost table): R = the upper Cholesky
+ * factor of A^T A (positive diagonal), Q = A R^{-1}.  passes = 2 gives
+ * CholeskyQR2: the same steps on Q, and R = R2 R1.  Provided for comparison:
+ * one pass loses orthogonality like cond(A)^2 u and breaks down (NaN in Q
+ * and R, not detected) once A^T A is not numerically positive definite.
+ *   dtype, m, n (m >= n >= 1, n <= 64); A: device m x n (lda >= n), read
+ *   only; Q: device m x n (ldq >= n), may be A itself; R: device n x n
+ *   (ldr >= n), zeros below the diagonal.  A stream-ordered workspace is
+ *   released at the end of the stream work.
+ *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 Q, 7 ldq,
+ *   8 R, 9 ldr, 10 passes. */
+int tsqr_cholqr(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+                int64_t ldr, int passes, void* stream);
+
 /* B <- Q B (reverse order of tsqr_apply_qt).  Same arguments. */
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
 

@@ -65,6 +65,7 @@ def load():
         "tsqr_apply_qt": [vp, i64, vp, i64, vp],
         "tsqr_apply_q": [vp, i64, vp, i64, vp],
         "tsqr_lstsq": [i32, i64, i64, vp, i64, i64, vp, i64, vp, popts, vp],
+        "tsqr_cholqr": [i32, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp],
         "tsqr_form_q": [vp, vp, i64, vp],
         "tsqr_qtree_destroy": [vp],
         "tsqr_qtree_info": [vp, p64],

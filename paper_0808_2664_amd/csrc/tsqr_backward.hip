@@ -8,6 +8,8 @@
 // The n x n work (M, C, R^{-1}) runs in one workgroup per matrix; R^{-1} uses
 // the same block recurrence as the T factors (inverse of an upper triangle:
 // T12 = -T11 U12 T22).  dA is one streaming pass over dQ and Q on MFMA.
+// CholeskyQR, the comparison algorithm of Sec. 2.3, is built from the same
+// Gram and streaming kernels.
 #include "tsqr_common.hpp"
 
 namespace tsqr {
@@ -215,6 +217,123 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(int64_t m, int n, const 
             }
         }
     }
+}
+
+// CholeskyQR (Sec. 2.3: the fast, conditionally stable alternative to TSQR):
+// R = upper Cholesky factor of G = A^T A, Q = A R^{-1}.  The Gram matrix and
+// the product A R^{-1} reuse k_gram / k_gram_reduce and k_adjoint_stream (with
+// X = 0 and Y = R^{-1}); this kernel does the n x n part in one workgroup:
+// Cholesky of G in LDS, R^{-1} column by column, and R written out, or
+// R Rprev when Rprev is given (the second pass of CholeskyQR2: R = R2 R1).
+// A pivot that is not positive gives NaN (sqrt of a negative), which
+// propagates to Q and R.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_chol_small(int n, const T* __restrict__ G, T* R, int64_t ldr, const T* Rprev,
+                                                    int64_t ldp, T* __restrict__ XY) {
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    __shared__ T Gs[NCP][NCP + 1];
+    __shared__ T Ui[NCP][NCP + 1];
+    __shared__ T Pv[NCP][NCP + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        Gs[i][j] = (i < n && j < n) ? G[i * NCP + j] : T(0);
+        Pv[i][j] = (Rprev && i < n && j < n && j >= i) ? Rprev[(int64_t)i * ldp + j] : T(0);
+    }
+    __syncthreads();
+    // right-looking Cholesky: row j of the upper triangle becomes row j of R
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) Gs[j][j] = sqrt(Gs[j][j]);
+        __syncthreads();
+        for (int c = j + 1 + tid; c < n; c += 256) Gs[j][c] /= Gs[j][j];
+        __syncthreads();
+        const int t = n - j - 1;
+        for (int e = tid; e < t * t; e += 256) {
+            const int i = j + 1 + e / t, c = j + 1 + e % t;
+            if (c >= i) Gs[i][c] -= Gs[j][i] * Gs[j][c];
+        }
+        __syncthreads();
+    }
+    // column c of R^{-1}: back substitution R x = e_c
+    if (tid < NCP) {
+        const int c = tid;
+        for (int i = NCP - 1; i >= 0; --i) {
+            T v = T(0);
+            if (c < n && i <= c) {
+                v = (i == c) ? T(1) : T(0);
+                for (int l = i + 1; l <= c; ++l) v -= Gs[i][l] * Ui[l][c];
+                v /= Gs[i][i];
+            }
+            Ui[i][c] = v;
+        }
+    }
+    __syncthreads();
+    T* X = XY;
+    T* Y = XY + NCP * NCP;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        X[e] = T(0);
+        Y[e] = Ui[i][j];
+        if (i < n && j < n) {
+            T v = T(0);
+            if (j >= i) {
+                if (Rprev) {
+                    for (int l = i; l <= j; ++l) v += Gs[i][l] * Pv[l][j];
+                } else {
+                    v = Gs[i][j];
+                }
+            }
+            R[(int64_t)i * ldr + j] = v;
+        }
+    }
+}
+
+template <typename T, int NC>
+static hipError_t cholqr_nc(int64_t m, int n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R, int64_t ldr,
+                            int passes, hipStream_t st) {
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    int64_t CR = (m + 2047) / 2048;
+    CR = ((CR + 255) / 256) * 256;
+    if (CR < 256) CR = 256;
+    const int64_t nch = (m + CR - 1) / CR;
+    const size_t bytes = (size_t)(nch + 1 + 2) * NCP * NCP * sizeof(T);
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, bytes, st);
+    if (e != hipSuccess) return e;
+    T* part = (T*)ws;
+    T* G = part + (size_t)nch * NCP * NCP;
+    T* XY = G + (size_t)NCP * NCP;
+    const T* src = A;
+    int64_t lds = lda;
+    for (int p = 0; p < passes; ++p) {
+        k_gram<T, NC><<<dim3((unsigned)nch, 1), 256, 0, st>>>(m, n, src, lds, 0, src, lds, 0, CR, part);
+        k_gram_reduce<T, NC><<<dim3((NCP * NCP + 63) / 64, 1), 256, 0, st>>>((int)nch, part, G);
+        k_chol_small<T, NC><<<1, 256, 0, st>>>(n, G, R, ldr, p > 0 ? R : nullptr, ldr, XY);
+        // Q = src R^{-1}; each wave reads its rows whole before writing them,
+        // so the second pass may run in place on Q
+        k_adjoint_stream<T, NC><<<dim3((unsigned)((m + 255) / 256), 1), 256, 0, st>>>(m, n, src, lds, 0, src, lds, 0,
+                                                                                      XY, Q, ldq, 0);
+        src = Q;
+        lds = ldq;
+    }
+    e = hipGetLastError();
+    hipError_t e2 = hipFreeAsync(ws, st);
+    return e != hipSuccess ? e : e2;
+}
+
+template <typename T>
+static hipError_t cholqr_t(int64_t m, int n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R, int64_t ldr, int passes,
+                           hipStream_t st) {
+    if (n <= 16) return cholqr_nc<T, 16>(m, n, A, lda, Q, ldq, R, ldr, passes, st);
+    if (n <= 32) return cholqr_nc<T, 32>(m, n, A, lda, Q, ldq, R, ldr, passes, st);
+    return cholqr_nc<T, 64>(m, n, A, lda, Q, ldq, R, ldr, passes, st);
+}
+
+hipError_t launch_cholqr(bool f64, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+                         int64_t ldr, int passes, hipStream_t st) {
+    if (f64)
+        return cholqr_t<double>(m, (int)n, (const double*)A, lda, (double*)Q, ldq, (double*)R, ldr, passes, st);
+    return cholqr_t<float>(m, (int)n, (const float*)A, lda, (float*)Q, ldq, (float*)R, ldr, passes, st);
 }
 
 template <typename T, int NC>

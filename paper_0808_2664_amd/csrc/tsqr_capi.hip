@@ -276,6 +276,23 @@ int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k,
     return rc;
 }
 
+int tsqr_cholqr(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+                int64_t ldr, int passes, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!Q) return -6;
+    if (ldq < n) return -7;
+    if (!R) return -8;
+    if (ldr < n) return -9;
+    if (passes != 1 && passes != 2) return -10;
+    hipError_t e = tsqr::launch_cholqr(dtype == TSQR_F64, m, n, A, lda, Q, ldq, R, ldr, passes, (hipStream_t)stream);
+    return e == hipSuccess ? 0 : hip_fail(e);
+}
+
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
     if (!q) return -1;
     if (k < 0) return -2;

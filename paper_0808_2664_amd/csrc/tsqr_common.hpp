@@ -112,6 +112,9 @@ hipError_t launch_trsm_upper(bool f64, int64_t n, const void* R, int64_t ldr, vo
                              hipStream_t st);
 hipError_t launch_colnorm(bool f64, int64_t r0, int64_t m, const void* B, int64_t ldb, int64_t k, void* rnorm,
                           hipStream_t st);
+// CholeskyQR (passes = 1) or CholeskyQR2 (passes = 2) of A into Q and R.
+hipError_t launch_cholqr(bool f64, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+                         int64_t ldr, int passes, hipStream_t st);
 hipError_t launch_backward(bool f64, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t sq,
                            const void* R, int64_t ldr, int64_t sr, const void* dQ, int64_t lddq, int64_t sdq,
                            const void* dR, int64_t lddr, int64_t sdr, void* dA, int64_t ldda, int64_t sda,

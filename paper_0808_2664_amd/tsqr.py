@@ -156,6 +156,20 @@ def lstsq(A: torch.Tensor, B: torch.Tensor, rnorm: bool = True, block_rows=0, ch
     return X, rn
 
 
+def cholqr(A: torch.Tensor, passes: int = 1, out_q: torch.Tensor | None = None):
+    """CholeskyQR (passes = 1) or CholeskyQR2 (passes = 2) of A (m x n,
+    n <= 64), for comparison with TSQR: returns (Q, R), diag(R) > 0.  A is not
+    modified unless out_q is A."""
+    lib = _lib.load()
+    m, n = A.shape
+    Q = out_q if out_q is not None else torch.empty(m, n, dtype=A.dtype, device=A.device)
+    R = torch.empty(n, n, dtype=A.dtype, device=A.device)
+    rc = lib.tsqr_cholqr(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(Q), _ld(Q), _ptr(R), _ld(R), int(passes),
+                         _stream(A))
+    _lib.check("tsqr_cholqr", rc)
+    return Q, R
+
+
 def sign_normalize(Q: torch.Tensor | None, R: torch.Tensor):
     """R <- D R, Q <- Q D with D = sign(diag R), sign(0) = +1 (in place)."""
     lib = _lib.load()

@@ -149,3 +149,21 @@ def test_lstsq_argument_errors_without_launch():
     assert f(1, 100, 4, fake, 4, 2, fake, 1, None, None, None) == -8           # ldb
     bad = _lib.opts(flags=2)
     assert f(1, 100, 4, fake, 4, 2, fake, 2, None, ctypes.byref(bad), None) == -10
+
+
+def test_cholqr_argument_errors_without_launch():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: every call below fails its checks first
+    f = lib.tsqr_cholqr
+    assert f(7, 100, 4, fake, 4, fake, 4, fake, 4, 1, None) == -1         # dtype
+    assert f(1, 3, 4, fake, 4, fake, 4, fake, 4, 1, None) == -2           # m < n
+    assert f(1, 100, 0, fake, 4, fake, 4, fake, 4, 1, None) == -3         # n
+    assert f(1, 100, 65, fake, 65, fake, 65, fake, 65, 1, None) == _lib.TSQR_ERR_UNSUPPORTED
+    assert f(1, 100, 4, None, 4, fake, 4, fake, 4, 1, None) == -4         # A
+    assert f(1, 100, 4, fake, 3, fake, 4, fake, 4, 1, None) == -5         # lda
+    assert f(1, 100, 4, fake, 4, None, 4, fake, 4, 1, None) == -6         # Q
+    assert f(1, 100, 4, fake, 4, fake, 3, fake, 4, 1, None) == -7         # ldq
+    assert f(1, 100, 4, fake, 4, fake, 4, None, 4, 1, None) == -8         # R
+    assert f(1, 100, 4, fake, 4, fake, 4, fake, 3, 1, None) == -9         # ldr
+    assert f(1, 100, 4, fake, 4, fake, 4, fake, 4, 3, None) == -10        # passes
