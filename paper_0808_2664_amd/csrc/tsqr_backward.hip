@@ -8,15 +8,16 @@
 // The n x n work (M, C, R^{-1}) runs in one workgroup per matrix; R^{-1} uses
 // the same block recurrence as the T factors (inverse of an upper triangle:
 // T12 = -T11 U12 T22).  dA is one streaming pass over dQ and Q on MFMA.
-// CholeskyQR, the comparison algorithm of Sec. 2.3, is built from the same
-// Gram and streaming kernels.
+// CholeskyQR, the comparison algorithm of Sec. 2.3, reuses the Gram kernels.
 #include "tsqr_common.hpp"
 
 namespace tsqr {
 using namespace dev;
 
-// Partial Gram dQ^T Q over rows [ch*CR, (ch+1)*CR) of matrix b.
-template <typename T, int NC>
+// Partial Gram dQ^T Q over rows [ch*CR, (ch+1)*CR) of matrix b.  SYM: dQ and
+// Q are the same matrix; only the tiles on and above the diagonal are formed
+// (the others are written as zeros) and the matrix is read once.
+template <typename T, int NC, bool SYM = false>
 __global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restrict__ dQ, int64_t lddq, int64_t sdq,
                                               const T* __restrict__ Q, int64_t ldq, int64_t sq, int64_t CR,
                                               T* __restrict__ part) {
@@ -45,12 +46,13 @@ __global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restr
                 const int cc = 16 * p + l16;
                 const bool ok = (r < hi) && (cc < n);
                 a[p] = ok ? dq[r * lddq + cc] : T(0);
-                bq[p] = ok ? q[r * ldq + cc] : T(0);
+                bq[p] = SYM ? a[p] : (ok ? q[r * ldq + cc] : T(0));
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
-                for (int c = 0; c < NP; ++c) acc[p][c] = M::mma(a[p], bq[c], acc[p][c]);
+                for (int c = 0; c < NP; ++c)
+                    if (!SYM || c >= p) acc[p][c] = M::mma(a[p], bq[c], acc[p][c]);
         }
     }
     T* out = part + ((int64_t)b * nch + ch) * NCP * NCP;
@@ -74,8 +76,10 @@ __global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restr
 
 // G[b] = sum over chunks of the partials, in a fixed order: wave w of a
 // workgroup adds chunks w, w + 4, w + 8, ... for 64 consecutive entries (one
-// per lane, so the loads are coalesced), then the four wave sums are added in
-// order.  Four independent streams per entry keep the loads in flight.
+// per lane, so the loads are coalesced) into four running sums (chunks
+// w + 16 t + 4 u go to sum u), then the sums and the four waves' results are
+// added in order.  Sixteen independent streams per entry keep the loads in
+// flight.
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_gram_reduce(int nch, const T* __restrict__ part, T* __restrict__ G) {
     constexpr int NCP = NC < 16 ? 16 : NC;
@@ -85,9 +89,16 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int nch, const T* __restric
     const int e = blockIdx.x * 64 + lane;
     const bool ok = e < NCP * NCP;
     const T* p = part + (int64_t)b * nch * NCP * NCP + (ok ? e : 0);
-    T s = T(0);
-    for (int c = wv; c < nch; c += 4) s += p[(int64_t)c * NCP * NCP];
-    red[wv][lane] = s;
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int c = wv;
+    for (; c + 12 < nch; c += 16) {
+        s0 += p[(int64_t)c * NCP * NCP];
+        s1 += p[(int64_t)(c + 4) * NCP * NCP];
+        s2 += p[(int64_t)(c + 8) * NCP * NCP];
+        s3 += p[(int64_t)(c + 12) * NCP * NCP];
+    }
+    for (; c < nch; c += 4) s0 += p[(int64_t)c * NCP * NCP];
+    red[wv][lane] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (wv == 0 && ok) G[(int64_t)b * NCP * NCP + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
@@ -220,9 +231,10 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(int64_t m, int n, const 
 }
 
 // CholeskyQR (Sec. 2.3: the fast, conditionally stable alternative to TSQR):
-// R = upper Cholesky factor of G = A^T A, Q = A R^{-1}.  The Gram matrix and
-// the product A R^{-1} reuse k_gram / k_gram_reduce and k_adjoint_stream (with
-// X = 0 and Y = R^{-1}); this kernel does the n x n part in one workgroup:
+// R = upper Cholesky factor of G = A^T A, Q = A R^{-1}.  The Gram matrix
+// reuses k_gram (symmetric form) and k_gram_reduce, the product A R^{-1} is
+// k_rmul_stream with R^{-1} taken from Y of XY; this kernel does the n x n
+// part in one workgroup:
 // Cholesky of G in LDS, R^{-1} column by column, and R written out, or
 // R Rprev when Rprev is given (the second pass of CholeskyQR2: R = R2 R1).
 // A pivot that is not positive gives NaN (sqrt of a negative), which
@@ -288,6 +300,59 @@ __global__ __launch_bounds__(256) void k_chol_small(int n, const T* __restrict__
     }
 }
 
+// Q = A M for the n x n upper triangle M = R^{-1} (CholeskyQR's second
+// step), over 512-row blocks (4 waves x 8 groups of 16 rows).  The K index of
+// MFMA step k4 in lane group l4 is NK l4 + k4, so a lane reads NK consecutive
+// entries of its row; the next group's rows are loaded while the current one
+// is multiplied.  A wave loads a group's rows whole before writing them, so Q
+// may be A itself.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_rmul_stream(int64_t m, int n, const T* A, int64_t lda,
+                                                     const T* __restrict__ Mg, T* Q, int64_t ldq) {
+    typedef Mfma<T> M;
+    typedef typename M::acc acc_t;
+    constexpr int NCP = NC < 16 ? 16 : NC;
+    constexpr int NP = NCP / 16;
+    constexpr int NK = NCP / 4;
+    constexpr int GR = 8;  // groups of 16 rows per wave
+    __shared__ T Ms[NCP][NCP + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    for (int e = tid; e < NCP * NCP; e += 256) {
+        const int i = e / NCP, j = e - i * NCP;
+        Ms[i][j] = Mg[e];
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (64 * GR) + (16 * GR) * wv;
+    T a[NK], an[NK];
+    auto load = [&](int g, T* dst) {
+        const int64_t rr = base + 16 * g + l16;
+#pragma unroll
+        for (int k4 = 0; k4 < NK; ++k4) {
+            const int cc = NK * l4 + k4;
+            dst[k4] = (rr < m && cc < n) ? A[rr * lda + cc] : T(0);
+        }
+    };
+    load(0, a);
+    for (int g = 0; g < GR; ++g) {
+        if (base + 16 * g >= m) break;
+        if (g + 1 < GR) load(g + 1, an);
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            acc_t u = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int k4 = 0; k4 < NK; ++k4) u = M::mma(a[k4], Ms[NK * l4 + k4][16 * c + l16], u);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = base + 16 * g + M::orow(l4, r);
+                const int col = 16 * c + l16;
+                if (row < m && col < n) Q[row * ldq + col] = u[r];
+            }
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < NK; ++k4) a[k4] = an[k4];
+    }
+}
+
 template <typename T, int NC>
 static hipError_t cholqr_nc(int64_t m, int n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R, int64_t ldr,
                             int passes, hipStream_t st) {
@@ -306,13 +371,12 @@ static hipError_t cholqr_nc(int64_t m, int n, const T* A, int64_t lda, T* Q, int
     const T* src = A;
     int64_t lds = lda;
     for (int p = 0; p < passes; ++p) {
-        k_gram<T, NC><<<dim3((unsigned)nch, 1), 256, 0, st>>>(m, n, src, lds, 0, src, lds, 0, CR, part);
+        k_gram<T, NC, true><<<dim3((unsigned)nch, 1), 256, 0, st>>>(m, n, src, lds, 0, src, lds, 0, CR, part);
         k_gram_reduce<T, NC><<<dim3((NCP * NCP + 63) / 64, 1), 256, 0, st>>>((int)nch, part, G);
         k_chol_small<T, NC><<<1, 256, 0, st>>>(n, G, R, ldr, p > 0 ? R : nullptr, ldr, XY);
-        // Q = src R^{-1}; each wave reads its rows whole before writing them,
-        // so the second pass may run in place on Q
-        k_adjoint_stream<T, NC><<<dim3((unsigned)((m + 255) / 256), 1), 256, 0, st>>>(m, n, src, lds, 0, src, lds, 0,
-                                                                                      XY, Q, ldq, 0);
+        // Q = src R^{-1} (Y of XY); each wave reads its rows whole before
+        // writing them, so the second pass may run in place on Q
+        k_rmul_stream<T, NC><<<(unsigned)((m + 511) / 512), 256, 0, st>>>(m, n, src, lds, XY + NCP * NCP, Q, ldq);
         src = Q;
         lds = ldq;
     }
