@@ -259,10 +259,13 @@ __global__ __launch_bounds__(256) void k_chol_small(int n, const T* __restrict__
         __syncthreads();
         for (int c = j + 1 + tid; c < n; c += 256) Gs[j][c] /= Gs[j][j];
         __syncthreads();
-        const int t = n - j - 1;
-        for (int e = tid; e < t * t; e += 256) {
-            const int i = j + 1 + e / t, c = j + 1 + e % t;
-            if (c >= i) Gs[i][c] -= Gs[j][i] * Gs[j][c];
+        // thread (column tid % 64, row phase tid / 64) updates rows i > j
+        {
+            const int c = tid & 63;
+            if (c > j && c < n) {
+                const T rjc = Gs[j][c];
+                for (int i = j + 1 + (tid >> 6); i <= c; i += 4) Gs[i][c] -= Gs[j][i] * rjc;
+            }
         }
         __syncthreads();
     }
@@ -357,7 +360,9 @@ template <typename T, int NC>
 static hipError_t cholqr_nc(int64_t m, int n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R, int64_t ldr,
                             int passes, hipStream_t st) {
     constexpr int NCP = NC < 16 ? 16 : NC;
-    int64_t CR = (m + 2047) / 2048;
+    // about 512 chunks: two workgroups per CU for the Gram, and a partial-sum
+    // buffer small enough (16 MB at n = 64) to be cheap to allocate per call
+    int64_t CR = (m + 511) / 512;
     CR = ((CR + 255) / 256) * 256;
     if (CR < 256) CR = 256;
     const int64_t nch = (m + CR - 1) / CR;
