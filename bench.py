@@ -14,6 +14,11 @@ Eq. TSQR_seq_runtime; apply Q^T to k columns 4mnk - 2n^2k; explicit Q
 2mn^2 - 2n^3/3).  The roofline object is for the dominant kernel (the chain
 factor kernel), timed with HIP events on its own stream; its algorithmic
 bytes are 2*8*m*n (A read once, reflectors written once: Table 4, 2mn words).
+
+Extra objects on the same line (each also alone with --extra NAME): CAQR of a
+16384^2 matrix with FP64 and FP32 updates, the batched plan of 2000 uneven
+matrices, forward against forward + backward of the differentiable TSQR,
+least squares through TSQR, and TSQR against CholeskyQR / CholeskyQR2.
 """
 from __future__ import annotations
 
