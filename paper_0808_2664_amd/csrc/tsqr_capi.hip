@@ -369,7 +369,11 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0};
         if (o.chains == 0) {
             const int64_t blocks = (rows + 63) / 64;
-            const int chain_blocks = chain_blocks_env > 0 ? chain_blocks_env : (rows >= 12288 ? 8 : 4);
+            // eight-block chains halve the update's tree steps against four;
+            // with the FP64 update, short panels take four so that their
+            // factor (on the critical path near the end) stays short
+            const int chain_blocks =
+                chain_blocks_env > 0 ? chain_blocks_env : ((!cf64 || rows >= 12288) ? 8 : 4);
             const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
         }
