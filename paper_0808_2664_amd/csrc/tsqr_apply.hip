@@ -531,6 +531,10 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 // k_qt_tree64 (level-1 node per workgroup, then the last arrival performs a
 // node), each wave owning a 16-column tile over all 64 slab rows as in
 // k_chain_apply_w; a step's Y_node and T_node are staged in LDS.
+// A node's reflector tails sit in the positions of a child's upper triangle
+// (Sec. 2.1: the stacked-triangle QR), so the 16 x 16 tiles of Y_node below
+// the block diagonal are exact zeros and their products are skipped (here
+// and in k_node_apply_w); the results are the same bits.
 template <typename S, typename C, int TW>
 __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
                                                           int64_t k, const S* __restrict__ Ynode,
@@ -603,7 +607,8 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
             for (int p = 0; p < 4; ++p) {
                 w[p] = sl[p];
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+                for (int kk = 0; kk < 16; ++kk)
+                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
             }
             acc_t nw[4];
 #pragma unroll
@@ -628,7 +633,7 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
                 for (int p = 0; p < 4; ++p)
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc)
-                        u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+                        if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
             }
@@ -709,7 +714,8 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
             w[p] = sl[p];
             if (MODE != MODE_FORMQ) {
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+                for (int kk = 0; kk < 16; ++kk)
+                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
             }
         }
         acc_t nw[4];
@@ -734,7 +740,8 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+                for (int kc = 0; kc < 4; ++kc)
+                    if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
             for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
         }
