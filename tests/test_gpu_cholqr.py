@@ -91,3 +91,36 @@ def test_cholqr_in_place():
     Qo, Ro = oracle.cholqr(A, 2)
     assert oracle.rel_err(Q.cpu().numpy(), Qo) <= 1e-12
     assert oracle.rel_err(R.cpu().numpy(), Ro) <= 1e-12
+
+
+def test_cholqr_single_column_closed_form():
+    # n = 1: R = ||a||, Q = a / ||a||
+    a = workloads.gaussian(7000, 1, 91)
+    _note("cholqr n = 1")
+    Q, R = cholqr(_dev(a), 2)
+    torch.cuda.synchronize()
+    nrm = np.linalg.norm(a)
+    assert abs(float(R[0, 0]) - nrm) <= 1e-13 * nrm
+    np.testing.assert_allclose(Q.cpu().numpy(), a / nrm, rtol=0, atol=1e-15)
+
+
+def test_cholqr_through_the_abi_with_padded_leading_dimensions():
+    import ctypes
+
+    from paper_0808_2664_amd import _lib
+    m, n = 12000, 40
+    A = workloads.gaussian(m, n, 92)
+    Aw = torch.zeros(m, n + 5, dtype=torch.float64, device="cuda")
+    Aw[:, :n] = _dev(A)
+    Qw = torch.zeros(m, n + 3, dtype=torch.float64, device="cuda")
+    Rw = torch.zeros(n, n + 9, dtype=torch.float64, device="cuda")
+    _note("cholqr through the ABI, lda = n + 5, ldq = n + 3, ldr = n + 9")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = _lib.load().tsqr_cholqr(_lib.TSQR_F64, m, n, ctypes.c_void_p(Aw.data_ptr()), n + 5,
+                                 ctypes.c_void_p(Qw.data_ptr()), n + 3, ctypes.c_void_p(Rw.data_ptr()), n + 9, 2, st)
+    assert rc == 0
+    torch.cuda.synchronize()
+    Qo, Ro = oracle.cholqr(A, 2)
+    assert oracle.rel_err(Qw[:, :n].cpu().numpy(), Qo) <= 1e-12
+    assert oracle.rel_err(Rw[:, :n].cpu().numpy(), Ro) <= 1e-12
+    assert float(Qw[:, n:].abs().max()) == 0.0 and float(Rw[:, n:].abs().max()) == 0.0

@@ -142,3 +142,41 @@ def test_lstsq_full_size_sampled_and_properties():
     assert _rel(X[:, cols].cpu().numpy(), Xo) <= 1e-12
     assert _rel(rn[cols].cpu().numpy(), rno) <= 1e-12
 
+
+
+def test_lstsq_single_column_closed_form():
+    # n = 1: x = a^T b / a^T a, residual ||b - a x||
+    a = workloads.gaussian(5000, 1, 61)
+    B = workloads.gaussian(5000, 3, 62)
+    _note("lstsq n = 1")
+    X, rn = lstsq(_dev(a), _dev(B))
+    torch.cuda.synchronize()
+    x = (a[:, 0] @ B) / (a[:, 0] @ a[:, 0])
+    np.testing.assert_allclose(X.cpu().numpy()[0], x, rtol=1e-12)
+    np.testing.assert_allclose(rn.cpu().numpy(), np.linalg.norm(B - a @ x[None, :], axis=0), rtol=1e-12)
+
+
+def test_lstsq_through_the_abi_with_padded_leading_dimensions():
+    # lda > n and ldb > k: views into wider row-major buffers, called through the C ABI
+    import ctypes
+
+    from paper_0808_2664_amd import _lib
+    m, n, k = 9000, 24, 5
+    A = workloads.gaussian(m, n, 63)
+    B = workloads.gaussian(m, k, 64)
+    Aw = torch.zeros(m, n + 7, dtype=torch.float64, device="cuda")
+    Bw = torch.zeros(m, k + 3, dtype=torch.float64, device="cuda")
+    Aw[:, :n] = _dev(A)
+    Bw[:, :k] = _dev(B)
+    rn = torch.empty(k, dtype=torch.float64, device="cuda")
+    _note("lstsq through the ABI, lda = n + 7, ldb = k + 3")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = _lib.load().tsqr_lstsq(_lib.TSQR_F64, m, n, ctypes.c_void_p(Aw.data_ptr()), n + 7, k,
+                                ctypes.c_void_p(Bw.data_ptr()), k + 3, ctypes.c_void_p(rn.data_ptr()), None, st)
+    assert rc == 0
+    torch.cuda.synchronize()
+    Xo, rno = oracle.lstsq(A, B)
+    assert _rel(Bw[:n, :k].cpu().numpy(), Xo) <= 1e-12
+    assert _rel(rn.cpu().numpy(), rno) <= 1e-12
+    # the padding columns are untouched
+    assert float(Bw[:, k:].abs().max()) == 0.0
