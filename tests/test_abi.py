@@ -167,3 +167,16 @@ def test_cholqr_argument_errors_without_launch():
     assert f(1, 100, 4, fake, 4, fake, 4, None, 4, 1, None) == -8         # R
     assert f(1, 100, 4, fake, 4, fake, 4, fake, 3, 1, None) == -9         # ldr
     assert f(1, 100, 4, fake, 4, fake, 4, fake, 4, 3, None) == -10        # passes
+
+
+def test_header_is_plain_c():
+    # the boundary is a C ABI: the header must compile as C99 (no C++ or torch types)
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    hdr = os.path.join(ROOT, "include", "tsqr.h")
+    p = subprocess.run([gcc, "-fsyntax-only", "-x", "c", "-std=c99", "-Wall", "-Werror", hdr],
+                       capture_output=True, text=True)
+    assert p.returncode == 0, p.stderr
