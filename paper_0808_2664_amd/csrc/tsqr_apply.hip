@@ -771,6 +771,17 @@ __global__ void k_init_formq(int64_t n, T* __restrict__ Q, int64_t ldq) {
     Q[i * ldq + j] = (i == j) ? T(1) : T(0);
 }
 
+// Layout of an apply with n = 64: the wide kernels (a 16-column tile over all
+// 64 rows per wave) hold one workgroup per CU; when that gives fewer
+// workgroups than CUs (few chains and few columns, e.g. the update of the
+// next panel's 64 columns in CAQR), the narrow kernels' four times as many
+// workgroups finish sooner.  One decision per apply (chains, tree levels).
+static bool use_wide(const Geom& g, int64_t k) {
+    if (g.n != 64 || k <= 16) return false;
+    const int64_t tw = k <= 32 ? 2 : 4;
+    return (int64_t)g.W * ((k + 16 * tw - 1) / (16 * tw)) >= 256;
+}
+
 template <typename S, typename C, int NC, int H, int MODE>
 static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, const Work& wk, S* B, int64_t ldb,
                                      int64_t k, hipStream_t st) {
@@ -782,7 +793,7 @@ static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, con
     phase_begin(1 + MODE, st);
     static_assert(H == 64, "the chain kernel takes 64-row blocks");
     if constexpr (NP == 4) {
-        if (g.n == 64 && k > 16) {
+        if (use_wide(g, k)) {
             // 16 TW columns per workgroup, TW = 2 or 4 waves
             const int tw = k <= 32 ? 2 : 4;
             const int ngroups = (int)((k + 16 * tw - 1) / (16 * tw));
@@ -807,7 +818,7 @@ template <typename S, typename C, int NC>
 static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ldb, int64_t k, hipStream_t st) {
     if (g.levels == 0) return hipSuccess;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
-    const bool wide = NP == 4 && g.n == 64 && k > 16;
+    const bool wide = NP == 4 && use_wide(g, k);
     const int tw = k <= 32 ? 2 : 4;  // waves (16-column tiles) per workgroup of the wide kernel
     const int ntiles = wide ? (int)((k + 16 * tw - 1) / (16 * tw)) : (int)((k + 15) / 16);  // column groups
     const int64_t nodes = (g.W + g.arity - 1) / g.arity;
@@ -887,7 +898,7 @@ static hipError_t node_apply_launch(const Geom& g, int lev, const Work& wk, S* B
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     constexpr int NP = NC <= 16 ? 1 : NC / 16;
     if constexpr (NP == 4) {
-        if (g.n == 64 && k > 16) {
+        if (use_wide(g, k)) {
             const int tw = k <= 32 ? 2 : 4;
             const int ngroups = (int)((k + 16 * tw - 1) / (16 * tw));
             const unsigned gw = (unsigned)(nodes * ngroups);
