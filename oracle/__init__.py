@@ -14,7 +14,11 @@ paper it follows is stated in ``oracle.c``; the conventions are:
 * comparisons are made after the sign normalisation ``D = sign(diag R)``,
   since the factorisation is unique only up to those signs (Sec. 2.1).
 
-``cholqr`` is the CholeskyQR the paper compares TSQR with (Sec. 2.3).
+``cholqr`` and ``mgs`` are the CholeskyQR and modified Gram-Schmidt the
+paper compares TSQR with (Sec. 2.3).  ``geqrf_blocked`` is the same
+Householder QR organised in panels with compact-WY trailing updates (the
+conventional blocked QR that CAQR reorganises, Sec. 3), multithreaded with
+OpenMP, for square matrices too large for the unblocked loop.
 ``qr_adjoint`` is not from the paper: it is the published QR adjoint
 (Walter & Lehmann; Liao et al. "copyltu" form).
 """
@@ -33,10 +37,12 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (ISO C99, no fast-math, no FMA contraction)."""
+    """Compile oracle.c with gcc (ISO C99, OpenMP, no fast-math, no FMA
+    contraction: the vectoriser may not reassociate sums, so every sum keeps
+    the order written in the C source)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+        cmd = ["gcc", "-std=c99", "-O3", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
@@ -57,10 +63,15 @@ def _load():
         lib.oracle_qr_adjoint.argtypes = [i64, i64, dp, dp, dp, dp, dp]
         lib.oracle_lstsq.argtypes = [i64, i64, i64, dp, dp, dp, dp]
         lib.oracle_cholqr.argtypes = [i64, i64, dp, dp, dp, ctypes.c_int]
+        lib.oracle_geqrf_blocked.argtypes = [i64, i64, dp, dp, i64]
+        lib.oracle_mgs.argtypes = [i64, i64, dp, dp, dp]
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         lib.oracle_psum.argtypes = [dp, i64]
         lib.oracle_psum.restype = ctypes.c_double
         for f in ("oracle_geqrf", "oracle_apply_qt", "oracle_apply_q",
-                  "oracle_form_q", "oracle_qr_adjoint", "oracle_lstsq", "oracle_cholqr"):
+                  "oracle_form_q", "oracle_qr_adjoint", "oracle_lstsq", "oracle_cholqr",
+                  "oracle_geqrf_blocked", "oracle_mgs"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -92,6 +103,22 @@ def geqrf(A):
     tau = np.zeros(n)
     _check(_load().oracle_geqrf(m, n, _p(YR), _p(tau)), "oracle_geqrf")
     return YR, tau
+
+
+def geqrf_blocked(A, nb: int = 64):
+    """Blocked Householder QR (panels of nb columns, compact-WY trailing
+    updates, OpenMP over trailing column blocks).  Same outputs as geqrf."""
+    YR = _f64(A).copy()
+    m, n = YR.shape
+    tau = np.zeros(n)
+    _check(_load().oracle_geqrf_blocked(m, n, _p(YR), _p(tau), int(nb)), "oracle_geqrf_blocked")
+    return YR, tau
+
+
+def set_threads(nthreads: int = 0) -> int:
+    """OpenMP threads of later oracle calls (0: the runtime default);
+    returns the count in effect."""
+    return int(_load().oracle_set_threads(int(nthreads)))
 
 
 def apply_qt(YR, tau, B):
@@ -186,6 +213,20 @@ def cholqr(A, passes: int = 1):
     if rc == -3:
         raise FloatingPointError("Cholesky pivot not positive")
     _check(rc, "oracle_cholqr")
+    return Q, R
+
+
+def mgs(A):
+    """Modified Gram-Schmidt: returns (Q, R), diag(R) > 0.  Raises
+    FloatingPointError if a column becomes exactly zero."""
+    A = _f64(A)
+    m, n = A.shape
+    Q = np.empty((m, n))
+    R = np.empty((n, n))
+    rc = _load().oracle_mgs(m, n, _p(A), _p(Q), _p(R))
+    if rc == -3:
+        raise FloatingPointError("zero column")
+    _check(rc, "oracle_mgs")
     return Q, R
 
 

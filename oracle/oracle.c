@@ -28,6 +28,9 @@
  * comment; at present every exported function is pinned by the CPU tests.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -72,12 +75,16 @@ static double pdot(scratch_t *s, const double *a, const double *b, int64_t n)
 
 /* Householder QR of a column-major m x n matrix (leading dimension m).
  * On exit: R on and above the diagonal, v(1:) below it (v(0) = 1 implicit),
- * tau[j] per column.  Returns 0, or -1 on allocation failure. */
+ * tau[j] per column.  Returns 0, or -1 on allocation failure.
+ * The updates of the columns k > j are independent of one another and are
+ * shared among OpenMP threads; each column's arithmetic is the same whatever
+ * the thread count, so the result does not depend on it. */
 static int geqr2_cm(int64_t m, int64_t n, double *a, double *tau)
 {
     scratch_t s = {0, 0};
     if (scratch_reserve(&s, m) != 0)
         return -1;
+    int fail = 0;
     for (int64_t j = 0; j < n && j < m; ++j) {
         double *x = a + j * m + j; /* column j, rows j..m-1 */
         int64_t len = m - j;
@@ -98,21 +105,37 @@ static int geqr2_cm(int64_t m, int64_t n, double *a, double *tau)
         if (tau[j] == 0.0)
             continue;
         /* apply H_j = I - tau v v^T to columns k > j, rows j..m-1 */
-        for (int64_t k = j + 1; k < n; ++k) {
-            double *c = a + k * m + j;
-            /* w = v^T c with v(0) = 1 */
-            s.p[0] = c[0];
-            for (int64_t i = 1; i < len; ++i)
-                s.p[i] = x[i] * c[i];
-            double w = psum(s.p, len);
-            double tw = tau[j] * w;
-            c[0] -= tw;
-            for (int64_t i = 1; i < len; ++i)
-                c[i] -= tw * x[i];
+        const double tj = tau[j];
+#pragma omp parallel if ((n - j - 1) * len > 65536)
+        {
+            scratch_t ts = {0, 0};
+            int ok = scratch_reserve(&ts, len) == 0;
+            if (!ok) {
+#pragma omp atomic write
+                fail = 1;
+            }
+#pragma omp for schedule(static)
+            for (int64_t k = j + 1; k < n; ++k) {
+                if (!ok)
+                    continue;
+                double *c = a + k * m + j;
+                /* w = v^T c with v(0) = 1 */
+                ts.p[0] = c[0];
+                for (int64_t i = 1; i < len; ++i)
+                    ts.p[i] = x[i] * c[i];
+                double w = psum(ts.p, len);
+                double tw = tj * w;
+                c[0] -= tw;
+                for (int64_t i = 1; i < len; ++i)
+                    c[i] -= tw * x[i];
+            }
+            free(ts.p);
         }
+        if (fail)
+            break;
     }
     free(s.p);
-    return 0;
+    return fail ? -1 : 0;
 }
 
 static double *to_cm(int64_t m, int64_t n, const double *rm)
@@ -451,6 +474,231 @@ int oracle_cholqr(int64_t m, int64_t n, const double *A, double *Q, double *R, i
     free(R1);
     free(R2);
     return rc;
+}
+
+/*
+ * Blocked Householder QR: the same factorisation as oracle_geqrf, organised
+ * as in LAPACK xGEQRF (right-looking, panels of nb columns).  This is the
+ * conventional QR that CAQR reorganises (Sec. 3: CAQR is blocked Householder
+ * QR whose panels are factored by TSQR, with the trailing matrix updated by
+ * the panel's reflectors), used as the reference for square matrices too
+ * large for the unblocked loop.  Per panel of jb columns starting at column k:
+ *  1. Householder QR of the panel A[k:m, k:k+jb] (geqr2_cm, pairwise sums);
+ *  2. T, the jb x jb upper triangular factor of the compact form
+ *     H_k ... H_{k+jb-1} = I - V T V^T (Schreiber and Van Loan, cited in
+ *     Sec. 2.1), by the forward recurrence T[j][j] = tau_j,
+ *     T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j), the inner products by
+ *     pairwise sums;
+ *  3. the trailing columns C = A[k:m, k+jb:n] <- Q_panel^T C
+ *     = C - V (T^T (V^T C)): W = V^T C, U = T^T W, C -= V U, each entry a
+ *     plain sum in index order.  The columns of C are shared among OpenMP
+ *     threads in blocks; every entry is computed by one thread in a fixed
+ *     order, so the result does not depend on the thread count.
+ * In exact arithmetic the result equals oracle_geqrf's (same reflectors, same
+ * tau, same R); in floating point only the summation order of step 3
+ * differs.  A: m x n row-major (m >= n), overwritten as by oracle_geqrf;
+ * tau: n entries; nb >= 1.  Returns 0, -1 for bad sizes, -2 on allocation
+ * failure.
+ */
+int oracle_geqrf_blocked(int64_t m, int64_t n, double *A, double *tau, int64_t nb)
+{
+    if (m < 0 || n < 0 || m < n || nb < 1)
+        return -1;
+    if (n == 0)
+        return 0;
+    const int64_t bmax = nb < n ? nb : n;
+    double *P = (double *)malloc((size_t)(m * bmax) * sizeof(double));   /* panel, column-major */
+    double *Vr = (double *)malloc((size_t)(m * bmax) * sizeof(double));  /* V, row-major */
+    double *T = (double *)malloc((size_t)(bmax * bmax) * sizeof(double));
+    scratch_t s = {0, 0};
+    if (!P || !Vr || !T || scratch_reserve(&s, m) != 0) {
+        free(P);
+        free(Vr);
+        free(T);
+        free(s.p);
+        return -2;
+    }
+    int rc = 0;
+    for (int64_t k = 0; k < n && rc == 0; k += nb) {
+        const int64_t jb = (n - k) < nb ? (n - k) : nb;
+        const int64_t mk = m - k;
+        /* 1. the panel */
+        for (int64_t i = 0; i < mk; ++i)
+            for (int64_t j = 0; j < jb; ++j)
+                P[j * mk + i] = A[(k + i) * n + k + j];
+        if (geqr2_cm(mk, jb, P, tau + k) != 0) {
+            rc = -2;
+            break;
+        }
+        for (int64_t i = 0; i < mk; ++i)
+            for (int64_t j = 0; j < jb; ++j)
+                A[(k + i) * n + k + j] = P[j * mk + i];
+        if (k + jb >= n)
+            break;
+        /* V row-major: unit diagonal, zeros above it */
+        for (int64_t i = 0; i < mk; ++i)
+            for (int64_t j = 0; j < jb; ++j)
+                Vr[i * jb + j] = (i > j) ? P[j * mk + i] : ((i == j) ? 1.0 : 0.0);
+        /* 2. T by the forward recurrence */
+        for (int64_t j = 0; j < jb; ++j) {
+            for (int64_t i = 0; i < jb; ++i)
+                T[i * jb + j] = 0.0;
+            T[j * jb + j] = tau[k + j];
+            if (tau[k + j] == 0.0)
+                continue;
+            for (int64_t l = 0; l < j; ++l) {
+                /* (V[:, l]^T v_j): rows i >= j, V[j][l] * 1 plus the tails */
+                const int64_t len = mk - j;
+                s.p[0] = P[l * mk + j];
+                for (int64_t i = 1; i < len; ++i)
+                    s.p[i] = P[l * mk + j + i] * P[j * mk + j + i];
+                T[l * jb + j] = psum(s.p, len); /* z_l, scaled below */
+            }
+            /* T[0:j, j] = -tau_j T[0:j, 0:j] z, rows in order (T upper) */
+            for (int64_t l = 0; l < j; ++l) {
+                double acc = 0.0;
+                for (int64_t q = l; q < j; ++q)
+                    acc += T[l * jb + q] * T[q * jb + j];
+                s.p[l] = -tau[k + j] * acc;
+            }
+            for (int64_t l = 0; l < j; ++l)
+                T[l * jb + j] = s.p[l];
+        }
+        /* 3. trailing columns, in blocks of CB per thread */
+        const int64_t c0 = k + jb, nc = n - c0;
+        enum { CB = 32 };
+        const int64_t nblk = (nc + CB - 1) / CB;
+        int fail = 0;
+#pragma omp parallel
+        {
+            double *W = (double *)malloc((size_t)(jb * CB) * sizeof(double));
+            double *U = (double *)malloc((size_t)(jb * CB) * sizeof(double));
+            if (!W || !U) {
+#pragma omp atomic write
+                fail = 1;
+            }
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t bk = 0; bk < nblk; ++bk) {
+                if (!W || !U)
+                    continue;
+                const int64_t cs = c0 + bk * CB;
+                const int64_t w = (n - cs) < CB ? (n - cs) : CB;
+                double srow[CB];
+                /* W = V^T C */
+                for (int64_t e = 0; e < jb * CB; ++e)
+                    W[e] = 0.0;
+                for (int64_t i = 0; i < mk; ++i) {
+                    const double *a = A + (k + i) * n + cs;
+                    const double *v = Vr + i * jb;
+                    for (int64_t j = 0; j < jb; ++j) {
+                        const double vij = v[j];
+                        double *wr = W + j * CB;
+                        for (int64_t c = 0; c < w; ++c)
+                            wr[c] += vij * a[c];
+                    }
+                }
+                /* U = T^T W: U[j][c] = sum_{l <= j} T[l][j] W[l][c] */
+                for (int64_t j = 0; j < jb; ++j) {
+                    double *ur = U + j * CB;
+                    for (int64_t c = 0; c < w; ++c)
+                        ur[c] = 0.0;
+                    for (int64_t l = 0; l <= j; ++l) {
+                        const double t = T[l * jb + j];
+                        const double *wr = W + l * CB;
+                        for (int64_t c = 0; c < w; ++c)
+                            ur[c] += t * wr[c];
+                    }
+                }
+                /* C -= V U, row by row */
+                for (int64_t i = 0; i < mk; ++i) {
+                    double *a = A + (k + i) * n + cs;
+                    const double *v = Vr + i * jb;
+                    for (int64_t c = 0; c < w; ++c)
+                        srow[c] = 0.0;
+                    for (int64_t j = 0; j < jb; ++j) {
+                        const double vij = v[j];
+                        const double *ur = U + j * CB;
+                        for (int64_t c = 0; c < w; ++c)
+                            srow[c] += vij * ur[c];
+                    }
+                    for (int64_t c = 0; c < w; ++c)
+                        a[c] -= srow[c];
+                }
+            }
+            free(W);
+            free(U);
+        }
+        if (fail)
+            rc = -2;
+    }
+    free(P);
+    free(Vr);
+    free(T);
+    free(s.p);
+    return rc;
+}
+
+/*
+ * Modified Gram-Schmidt, the other unstable alternative of the paper's
+ * comparison (Sec. 2.3, with CholeskyQR; its loss of orthogonality grows with
+ * the condition number).  Textbook right-looking form: for j = 0..n-1,
+ * R_jj = ||a_j||, q_j = a_j / R_jj, then for every later column c,
+ * R_jc = q_j^T a_c and a_c -= R_jc q_j (a_c being the column as already
+ * updated by q_0..q_{j-1}).  Sums over the m rows are pairwise.
+ * Inputs row-major: A m x n.  Outputs: Q m x n, R n x n (zeros below the
+ * diagonal).  Returns 0, -1 for bad sizes, -2 on allocation failure, -3 if a
+ * column becomes exactly zero (rank deficiency: R_jj = 0).
+ */
+int oracle_mgs(int64_t m, int64_t n, const double *A, double *Q, double *R)
+{
+    if (m < 0 || n < 0 || m < n)
+        return -1;
+    double *ac = to_cm(m, n, A);
+    scratch_t s = {0, 0};
+    if (!ac || scratch_reserve(&s, m > 0 ? m : 1) != 0) {
+        free(ac);
+        free(s.p);
+        return -2;
+    }
+    memset(R, 0, (size_t)(n * n) * sizeof(double));
+    int rc = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double *q = ac + j * m;
+        double nrm = sqrt(pdot(&s, q, q, m));
+        if (nrm == 0.0) {
+            rc = -3;
+            break;
+        }
+        R[j * n + j] = nrm;
+        for (int64_t i = 0; i < m; ++i)
+            q[i] /= nrm;
+        for (int64_t c = j + 1; c < n; ++c) {
+            double *a = ac + c * m;
+            double r = pdot(&s, q, a, m);
+            R[j * n + c] = r;
+            for (int64_t i = 0; i < m; ++i)
+                a[i] -= r * q[i];
+        }
+    }
+    if (rc == 0)
+        from_cm(m, n, ac, Q);
+    free(ac);
+    free(s.p);
+    return rc;
+}
+
+/* Number of OpenMP threads for later calls (<= 0: the runtime's default);
+ * returns the number the runtime will use. */
+int oracle_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
 }
 
 /* Exposed for the tests: pairwise sum of n doubles. */

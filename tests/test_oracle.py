@@ -387,3 +387,102 @@ def test_adjoint_ignores_lower_part_of_dR():
     a1 = oracle.qr_adjoint(Q, R, dQ, dR)
     a2 = oracle.qr_adjoint(Q, R, dQ, np.triu(dR))
     np.testing.assert_array_equal(a1, a2)
+
+
+# ---------------------------------------------------------------- blocked Householder QR
+
+@pytest.mark.parametrize("nb", [1, 2, 64])
+def test_blocked_hand_3x2(nb):
+    # panels of one or two columns: the compact form with T = tau (nb = 1) and
+    # the 2 x 2 T of the whole matrix give the hand-worked reflectors and R
+    g = _load("householder_3x2.json")
+    YR, tau = oracle.geqrf_blocked(_fmat(g["A"]), nb)
+    np.testing.assert_allclose(tau, [_frac(t) for t in g["tau"]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(oracle.r_of(YR), _fmat(g["R_raw"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(YR[1:, 0], [_frac(v) for v in g["v_tails"][0]], atol=1e-15)
+    np.testing.assert_allclose(YR[2:, 1], [_frac(v) for v in g["v_tails"][1]], atol=1e-15)
+
+
+def test_blocked_hand_combine_4x2():
+    g = _load("combine_4x2.json")
+    YR, tau = oracle.geqrf_blocked(_fmat(g["stacked"]), 1)
+    np.testing.assert_allclose(tau, [_frac(t) for t in g["tau"]], atol=1e-15)
+    np.testing.assert_allclose(oracle.r_of(YR), _fmat(g["R_raw"]), atol=1e-15)
+
+
+@pytest.mark.parametrize("m,n,nb", [(300, 200, 16), (257, 130, 64), (1000, 700, 64), (5000, 96, 32),
+                                    (64, 64, 64), (129, 128, 64), (2048, 2048, 64)])
+def test_blocked_matches_unblocked(m, n, nb):
+    # same reflectors, tau and R as the unblocked loop up to rounding: a
+    # transposed T, a wrong recurrence sign or a skipped trailing column
+    # fails here (n > nb in every case but one)
+    A = workloads.gaussian(m, n, 70 + n)
+    Y1, t1 = oracle.geqrf(A)
+    Y2, t2 = oracle.geqrf_blocked(A, nb)
+    assert oracle.rel_err(oracle.r_of(Y2), oracle.r_of(Y1)) < 1e-14
+    np.testing.assert_allclose(t2, t1, rtol=0, atol=1e-12)
+    L1, L2 = np.tril(Y1, -1), np.tril(Y2, -1)
+    assert np.linalg.norm(L2 - L1) <= 1e-12 * np.linalg.norm(L1)
+
+
+def test_blocked_invariants_and_thread_count():
+    A = workloads.gaussian(1500, 1500, 77)
+    Y, tau = oracle.geqrf_blocked(A, 64)
+    Q = oracle.form_q(Y, tau)
+    R = oracle.r_of(Y)
+    assert oracle.residual(A, Q, R) < 1e-14
+    assert oracle.orthogonality(Q) < 1e-12
+    # R^T R = A^T A (Sec. 4 Cor. 1: R is the Cholesky factor of A^T A up to signs)
+    assert np.linalg.norm(R.T @ R - A.T @ A) <= 1e-13 * np.linalg.norm(A) ** 2
+    # every entry is computed by one thread in a fixed order
+    nt = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        Y1, t1 = oracle.geqrf_blocked(A[:700, :600], 64)
+        oracle.set_threads(max(2, nt))
+        Y2, t2 = oracle.geqrf_blocked(A[:700, :600], 64)
+    finally:
+        oracle.set_threads(nt)
+    np.testing.assert_array_equal(Y1, Y2)
+    np.testing.assert_array_equal(t1, t2)
+
+
+# ---------------------------------------------------------------- modified Gram-Schmidt
+
+def test_mgs_hand_3x2():
+    g = _load("householder_3x2.json")
+    Q, R = oracle.mgs(_fmat(g["A"]))
+    np.testing.assert_allclose(R, _fmat(g["R_normalised"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Q, _fmat(g["Q_normalised"]), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("m,n,seed", [(3, 2, 0), (6, 3, 2), (8, 4, 3), (5, 1, 4)])
+def test_mgs_decimal_gram_schmidt(m, n, seed):
+    A = workloads.gaussian(m, n, 100 + seed)
+    Qx, Rx = _gs_decimal(A)
+    Q, R = oracle.mgs(A)
+    assert oracle.rel_err(R, Rx) < 1e-15
+    assert np.max(np.abs(Q - Qx)) < 1e-14
+
+
+def test_mgs_closed_form_and_orthogonality_loss():
+    # A = U T: R = T, Q = U
+    m, n = 400, 6
+    U = np.linalg.qr(workloads.gaussian(m, n, 81))[0]
+    T = np.triu(np.arange(1, n * n + 1, dtype=np.float64).reshape(n, n) % 5 + 1)
+    Q, R = oracle.mgs(U @ T)
+    np.testing.assert_allclose(R, T, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(Q, U, rtol=0, atol=1e-13)
+    # well conditioned: the Householder R; at cond 1e7 orthogonality is lost
+    # in proportion to cond * u (MGS), not cond^2 * u (classical Gram-Schmidt
+    # or CholeskyQR would exceed the upper bound)
+    A = workloads.gaussian(3000, 16, 82)
+    Q, R = oracle.mgs(A)
+    assert oracle.rel_err(R, oracle.qr(A)[1]) < 1e-13
+    assert oracle.orthogonality(Q) < 1e-13
+    B = workloads.conditioned(3000, 16, 1e7, 83, 84)
+    Qb, Rb = oracle.mgs(B)
+    assert 1e-12 < oracle.orthogonality(Qb) < 1e-6
+    assert oracle.residual(B, Qb, Rb) < 1e-14
+    with pytest.raises(FloatingPointError):
+        oracle.mgs(np.zeros((5, 2)))
