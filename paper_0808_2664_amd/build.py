@@ -1,7 +1,10 @@
 """Build libtsqr.so (HIP, gfx950) in-tree with hipcc.
 
 Every .hip file under csrc/ is compiled to an object in parallel, then linked
-into paper_0808_2664_amd/libtsqr.so.  Run: ``python -m paper_0808_2664_amd.build``.
+into paper_0808_2664_amd/libtsqr.so.  tsqr_factor_inst.hip is compiled once per
+instantiation of the factor launcher (type x panels x implicit Q kept), so the
+unrolled factor kernels build in parallel.  Run:
+``python -m paper_0808_2664_amd.build``.
 """
 from __future__ import annotations
 
@@ -25,13 +28,31 @@ CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Wno-unused-command-line-argument"]
 
 
+INST = "tsqr_factor_inst.hip"
+FACTOR_INST = [(t, np_, wq) for t in ("double", "float") for np_ in (4, 2, 1) for wq in (1, 0)]
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    """(source, object name, extra flags) of every compilation unit."""
+    units = []
+    for f in sorted(os.listdir(CSRC)):
+        if not f.endswith(".hip"):
+            continue
+        src = os.path.join(CSRC, f)
+        if f == INST:
+            for t, np_, wq in FACTOR_INST:
+                units.append((src, "factor_%s_np%d_%s" % (t[0], np_, "q" if wq else "r"),
+                              ["-DTSQR_INST_T=" + t, "-DTSQR_INST_NP=%d" % np_, "-DTSQR_INST_WQ=%d" % wq]))
+        else:
+            units.append((src, f[:-4], []))
+    # longest compilations first
+    return sorted(units, key=lambda u: 0 if u[1].startswith("factor_d") else 1)
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+def _compile(unit) -> str:
+    src, name, extra = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC] + CFLAGS + extra + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, p.stderr))

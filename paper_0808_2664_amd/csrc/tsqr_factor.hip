@@ -11,25 +11,6 @@
 
 namespace tsqr {
 
-// Waves per SIMD the factor kernel is compiled for (register budget 512/occ):
-// the FP64 tile of a 64 x 64 block takes 128 registers per lane and the
-// kernel needs the whole file; the FP32 kernel fits two waves per SIMD.
-template <typename T>
-struct WaveOcc {
-    static constexpr int value = sizeof(T) == 8 ? 1 : 2;
-};
-
-// PIPE: the panel-pipelined binary tree; launched cooperatively, so that
-// every wave is resident and a node's wave may wait for its children.
-template <typename T, int NP, int SG, bool PIPE, bool WQ>
-__global__ __launch_bounds__(64, WaveOcc<T>::value) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
-                                                     T* __restrict__ T_blk, T* __restrict__ Rbuf,
-                                                     T* __restrict__ Ynode, T* __restrict__ Tnode,
-                                                     T* __restrict__ tau_node, TreeArgs ta) {
-    __shared__ WSmem<T, NP> sm;
-    wave_tsqr<T, NP, SG, PIPE, WQ>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
-}
-
 __global__ void k_zero_i32(int* __restrict__ p, int64_t count) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -58,44 +39,24 @@ int wave_default_h(int NC) {
     return 64;
 }
 
-// Workgroups of k_wave_tsqr<T, NP, SG, true, WQ> the device keeps resident at once.
 template <typename T, int NP, int SG, bool WQ>
-static int64_t pipe_capacity() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    static int64_t cap[64];
-    static bool done[64];
-    if (dev < 0 || dev >= 64) return 0;
-    if (!done[dev]) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true, WQ>, 64, 0) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-            (void)hipGetLastError();
-            per_cu = 0;
-        }
-        cap[dev] = (int64_t)per_cu * cus;
-        done[dev] = true;
-    }
-    return cap[dev];
-}
-
-template <typename T, int NP, int SG, bool WQ>
-static hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
-    T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
-    T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
-    const bool pipe = g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ>();
-    if (pipe) {
-        Geom gg = g;
-        TreeArgs tt = ta;
-        void* args[] = {&gg, &A, &lda, &tau_blk, &T_blk, &Rbuf, &Ynode, &Tnode, &tau_node, &tt};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true, WQ>, dim3(g.W), dim3(64),
-                                                  args, 0, st);
-        if (e == hipSuccess) return hipSuccess;
-        (void)hipGetLastError();  // not co-resident after all: reduce level by level
-    }
-    k_wave_tsqr<T, NP, SG, false, WQ><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
-    return hipGetLastError();
-}
+hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st);
+// defined in tsqr_factor_inst.hip, one object per instantiation
+#define TSQR_FACTOR_EXTERN(T, NP, WQ) \
+    extern template hipError_t launch_wave<T, NP, 4, WQ>(const Geom&, T*, int64_t, const Work&, const TreeArgs&, hipStream_t);
+TSQR_FACTOR_EXTERN(double, 1, true)
+TSQR_FACTOR_EXTERN(double, 2, true)
+TSQR_FACTOR_EXTERN(double, 4, true)
+TSQR_FACTOR_EXTERN(double, 1, false)
+TSQR_FACTOR_EXTERN(double, 2, false)
+TSQR_FACTOR_EXTERN(double, 4, false)
+TSQR_FACTOR_EXTERN(float, 1, true)
+TSQR_FACTOR_EXTERN(float, 2, true)
+TSQR_FACTOR_EXTERN(float, 4, true)
+TSQR_FACTOR_EXTERN(float, 1, false)
+TSQR_FACTOR_EXTERN(float, 2, false)
+TSQR_FACTOR_EXTERN(float, 4, false)
+#undef TSQR_FACTOR_EXTERN
 
 template <typename T, bool WQ>
 static hipError_t factor_t(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
