@@ -57,7 +57,7 @@ def parse():
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, CAQR and forward+backward measurements")
-    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "lstsq", "cholqr"), default=None,
+    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "config1", "lstsq", "cholqr"), default=None,
                    help="run only this measurement and print its JSON (for profiling it)")
     return p.parse_args()
 
@@ -97,23 +97,46 @@ def traffic_from_profile(m, n):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(rows, n, k):
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
+
+def cpu_baseline(rows, n, k):
+    """The oracle (plain C, FP64, pairwise sums) on a bounded sample of the
+    step's workload: factor, Q^T B and the explicit Q of the first `rows`
+    rows, once with all the host's cores (OpenMP over independent columns)
+    and once single-threaded."""
     import oracle
     import workloads
     A = workloads.conditioned(rows, n, 1e8, 2, 3)
     B = workloads.gaussian(rows, k, 4)
-    t0 = time.perf_counter()
-    YR, tau = oracle.geqrf(A)
-    oracle.apply_qt(YR, tau, B)
-    oracle.form_q(YR, tau)
-    dt = time.perf_counter() - t0
     f = sum(flops(rows, n, k))
-    del np
-    return {"value": round(f / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "factor + apply_qt(k=%d) + form_q on %d x %d FP64 (cond 1e8), single-threaded C, %.2f s"
-                      % (k, rows, n, dt)}
+
+    def once():
+        t0 = time.perf_counter()
+        YR, tau = oracle.geqrf(A)
+        oracle.apply_qt(YR, tau, B)
+        oracle.form_q(YR, tau)
+        return time.perf_counter() - t0
+    nt = oracle.set_threads(0)
+    try:
+        dt_all = once()
+        oracle.set_threads(1)
+        dt_one = once()
+    finally:
+        oracle.set_threads(nt)
+    return {"value": round(f / dt_all / 1e9, 4), "unit": "GFLOP/s", "cores": nt, "kind": "oracle",
+            "sample": "factor + apply_qt(k=%d) + form_q on %d x %d FP64 (cond 1e8), C with OpenMP, %d threads, "
+                      "%.2f s" % (k, rows, n, nt, dt_all),
+            "single_thread": {"value": round(f / dt_one / 1e9, 4), "seconds": round(dt_one, 2)},
+            "cpu": cpu_model()}
 
 
 def main():
@@ -126,8 +149,8 @@ def main():
     import torch
     if a.extra:
         import paper_0808_2664_amd as tq_x
-        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "lstsq": bench_lstsq,
-              "cholqr": bench_cholqr}[a.extra]
+        fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "config1": bench_config1,
+              "lstsq": bench_lstsq, "cholqr": bench_cholqr}[a.extra]
         print(json.dumps({a.extra: fn(tq_x, torch, np)}), flush=True)
         return
 
@@ -227,7 +250,7 @@ def main():
     extras = {}
     if not a.no_extras:
         for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd),
-                         ("lstsq", bench_lstsq), ("cholqr", bench_cholqr)):
+                         ("config1", bench_config1), ("lstsq", bench_lstsq), ("cholqr", bench_cholqr)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn(tq, torch, np)
             torch.cuda.empty_cache()
@@ -259,7 +282,7 @@ def main():
         "hbm_gbs_step": round(sum(by) / (ms / 1e3) / 1e9, 1),
         "residual": res,
         "orthogonality": orth,
-        "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
+        "host": {"cpu": cpu_model(), "nproc": os.cpu_count()},
     }
     out.update(extras)
     print(json.dumps(out))
@@ -303,11 +326,11 @@ def bench_batched(tq, torch, np):
             for w, x in zip(work, src):
                 w.copy_(x)
         ts = []
-        for _ in range(3):
+        for _ in range(5):
             reset()
             torch.cuda.synchronize()
             ts.append(_ev_ms(torch, run_batched, 1))
-        t_b = sorted(ts)[1]
+        t_b = sorted(ts)[len(ts) // 2]
         reset()
         torch.cuda.synchronize()
 
@@ -315,7 +338,12 @@ def bench_batched(tq, torch, np):
             # the same work as the batch: R and the leaf reflectors, no implicit Q
             for w in work:
                 tq.factor(w, want_q=False)
-        t_s = _ev_ms(torch, run_seq, 1)
+        tss = []
+        for _ in range(3):
+            reset()
+            torch.cuda.synchronize()
+            tss.append(_ev_ms(torch, run_seq, 1))
+        t_s = sorted(tss)[1]
         # worst R error against the oracle on a sample (smallest, largest, an n = 64 one)
         reset()
         Rs = plan.factor(work)
@@ -328,8 +356,9 @@ def bench_batched(tq, torch, np):
             Ro = oracle.qr(src[i].double().cpu().numpy())[1]
             worst = max(worst, oracle.rel_err(R * oracle.signs(R)[:, None], Ro))
         gbs = alg / (t_b / 1e3) / 1e9
-        res[name] = {"ms": round(t_b, 3), "alg_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                     "sequential_ms": round(t_s, 3), "speedup_vs_sequential": round(t_s / t_b, 2),
+        res[name] = {"ms": round(t_b, 3), "runs": len(ts), "alg_gbs": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "sequential_ms": round(t_s, 3),
+                     "sequential_runs": len(tss), "speedup_vs_sequential": round(t_s / t_b, 2),
                      "worst_sampled_R_error": worst, "sample": sample, "plan": plan.info()}
         plan.close()
         del src, work
@@ -337,16 +366,22 @@ def bench_batched(tq, torch, np):
     return res
 
 
-def bench_caqr(tq, torch, np):
-    """Config 3: CAQR of a 16384 x 16384 N(0,1) matrix (seed 5, drawn on the
-    device), panel 64, trailing updates in FP64 and in FP32 (FP32 MFMA, FP64
-    storage).  Backward error ||A - QR||/||A|| through the GPU's implicit Q."""
+def bench_caqr(tq, torch, np, oracle_check=True):
+    """Config 3: CAQR of a 16384 x 16384 N(0,1) matrix (seed 5, drawn with
+    numpy on the host and copied to the device once), panel 64, trailing
+    updates in FP64 and with FP32 products on FP64 storage.  Time: median of
+    10 factorisations each (each on a fresh copy of A).  Errors per result:
+    backward error ||A - QR||/||A|| through the GPU's implicit Q, and the
+    normwise error of the sign-normalised R against the oracle's blocked
+    Householder QR of the same matrix (run on the host after the timings)."""
+    import oracle
+    import workloads
     N = 16384
-    g = torch.Generator(device="cuda").manual_seed(5)
-    A0 = torch.randn(N, N, dtype=torch.float64, device="cuda", generator=g)
+    A_np = workloads.cfg3(N)
+    A0 = torch.from_numpy(A_np).cuda()
     fl = 4.0 * N ** 3 / 3.0
-    res = {"workload": "CAQR 16384 x 16384 FP64 storage, panel 64", "flops": fl}
-    R64 = None
+    res = {"workload": "CAQR 16384 x 16384 FP64 storage, panel 64, N(0,1) seed 5", "flops": fl}
+    Rkeep = {}
     for name, upd, peak in (("f64_update", torch.float64, FP64_PEAK_TFLOPS), ("f32_update", torch.float32,
                                                                                FP32_PEAK_TFLOPS)):
         A = A0.clone()
@@ -363,12 +398,14 @@ def bench_caqr(tq, torch, np):
         run()
         box["qt"].close()
         ts = []
-        for _ in range(2):
+        reps = 10
+        for r in range(reps):
             run()
             ts.append(box["ms"])
-            if len(ts) < 2:
+            if r + 1 < reps:
                 box["qt"].close()
-        ms = min(ts)
+        ts.sort()
+        ms = ts[len(ts) // 2]
         R, qt = box["R"], box["qt"]
         X = torch.zeros(N, N, dtype=torch.float64, device="cuda")
         X.copy_(torch.triu(R))
@@ -377,49 +414,93 @@ def bench_caqr(tq, torch, np):
         qt.close()
         del X
         tfl = fl / (ms / 1e3) / 1e12
-        ent = {"ms": round(ms, 2), "tflops": round(tfl, 2), "frac_peak": round(tfl / peak, 4),
-               "peak_tflops": peak, "backward_error": be}
-        Rn = R * torch.sign(torch.where(torch.diagonal(R) == 0, torch.ones_like(torch.diagonal(R)),
-                                        torch.diagonal(R)))[:, None]
-        if R64 is None:
-            R64 = Rn
-        else:
-            ent["R_error_vs_f64_update"] = (torch.linalg.norm(Rn - R64) / torch.linalg.norm(R64)).item()
-        res[name] = ent
+        res[name] = {"ms": round(ms, 2), "ms_min_max": [round(ts[0], 2), round(ts[-1], 2)], "runs": reps,
+                     "tflops": round(tfl, 2), "frac_peak": round(tfl / peak, 4), "peak_tflops": peak,
+                     "backward_error": be}
+        Rkeep[name] = R.cpu().numpy()
         del A, R
         torch.cuda.empty_cache()
+    del A0
+    torch.cuda.empty_cache()
+    if oracle_check:
+        print("bench: caqr oracle (blocked Householder QR on the host)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        threads = oracle.set_threads(0)
+        YR, _ = oracle.geqrf_blocked(A_np, 64)
+        Ro = oracle.r_of(YR)
+        del YR
+        Ro *= oracle.signs(Ro)[:, None]
+        for name, R in Rkeep.items():
+            res[name]["R_error_vs_oracle"] = oracle.rel_err(R * oracle.signs(R)[:, None], Ro)
+        res["oracle"] = {"kind": "blocked Householder QR, panels of 64, FP64", "threads": threads,
+                         "seconds": round(time.perf_counter() - t0, 1)}
     return res
 
 
 def bench_fwd_bwd(tq, torch, np):
-    """Config 5: differentiable TSQR of 262144 x 32 FP64 (seed 7; dQ, dR seeds
-    8, 9): forward alone against forward + backward."""
+    """Config 5: differentiable TSQR, forward alone against forward +
+    backward, on 262144 x 32 FP64 (seed 7; dQ, dR seeds 8, 9) and on the
+    FP32 batch of 256 matrices of 8192 x 32 (seed 10; one batched
+    factorisation, each member on its own tree, then one explicit-Q pass and
+    the batched adjoint)."""
     import workloads
+    res = {"workload": "TSQR forward (factor + Q) and backward (QR adjoint): 262144 x 32 FP64; "
+                       "batch of 256 x 8192 x 32 FP32"}
     A_np, dQ_np, dR_np = workloads.cfg5()
-    A = torch.from_numpy(A_np).cuda()
-    dQ = torch.from_numpy(dQ_np).cuda()
-    dR = torch.from_numpy(dR_np).cuda()
+    Ab_np, dQb_np, dRb_np = workloads.cfg5_batch()
+    for name, (a_np, dq_np, dr_np), es in (("f64", (A_np, dQ_np, dR_np), 8), ("f32_batch", (Ab_np, dQb_np, dRb_np), 4)):
+        A = torch.from_numpy(a_np).cuda()
+        dQ = torch.from_numpy(dq_np).cuda()
+        dR = torch.from_numpy(dr_np).cuda()
 
-    def fwd():
-        tq.tsqr(A)
+        def fwd():
+            tq.tsqr(A)
 
-    Ag = A.clone().requires_grad_(True)
+        Ag = A.clone().requires_grad_(True)
 
-    def fwd_bwd():
-        Q, R = tq.tsqr(Ag)
-        torch.autograd.backward((Q, R), (dQ, dR))
-    for f in (fwd, fwd_bwd):
-        f()
-    # small problem: host launch gaps are a visible part of each call, so
-    # take the median of many calls
-    t_f = _ev_ms(torch, fwd, 21)
-    t_fb = _ev_ms(torch, fwd_bwd, 21)
-    m, n = A.shape
-    # HBM words: forward reads A, writes Y, reads Y, writes Q; backward reads Q, R, dQ, writes dA
-    fb_bytes = 8.0 * m * n * (4 + 3)
-    return {"workload": "TSQR forward (factor + Q) and backward (QR adjoint), 262144 x 32 FP64",
-            "fwd_ms": round(t_f, 4), "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3),
-            "fwd_bwd_alg_gbs": round(fb_bytes / (t_fb / 1e3) / 1e9, 1)}
+        def fwd_bwd():
+            Q, R = tq.tsqr(Ag)
+            torch.autograd.backward((Q, R), (dQ, dR))
+        for f in (fwd, fwd_bwd):
+            f()
+        # host launch gaps are a visible part of each call: median of many calls
+        t_f = _ev_ms(torch, fwd, 21)
+        t_fb = _ev_ms(torch, fwd_bwd, 21)
+        elems = float(A.numel())
+        # HBM words: forward reads A, writes Y, reads Y, writes Q; backward reads Q, dQ, writes dA (+ R, dR)
+        fb_bytes = es * elems * (4 + 3)
+        res[name] = {"shape": list(A.shape), "fwd_ms": round(t_f, 4), "fwd_bwd_ms": round(t_fb, 4),
+                     "ratio": round(t_fb / t_f, 3), "fwd_bwd_alg_gbs": round(fb_bytes / (t_fb / 1e3) / 1e9, 1)}
+        del A, dQ, dR, Ag
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_config1(tq, torch, np):
+    """Config 1: TSQR of one 4096 x 16 FP64 matrix (seed 1), leaves of 256
+    rows (16 chains, binary tree), R and the explicit Q: microseconds per
+    call (median of 200).  At this size the call is bound by launch and
+    synchronisation latency, not by HBM or arithmetic, so no roofline
+    fraction is given."""
+    import workloads
+    A0 = torch.from_numpy(workloads.cfg1()).cuda()
+    A = A0.clone()
+    Q = torch.empty_like(A0)
+
+    def call():
+        A.copy_(A0)
+        R, qt = tq.factor(A, chains=16)
+        qt.form_q(Q)
+        qt.close()
+
+    def copy_only():
+        A.copy_(A0)
+    for _ in range(5):
+        call()
+    t = _ev_ms(torch, call, 200)
+    t0 = _ev_ms(torch, copy_only, 200)
+    return {"workload": "TSQR 4096 x 16 FP64, 16 chains of 256 rows, factor + form_q", "us_per_call": round(1e3 * (t - t0), 2),
+            "us_per_call_with_copy": round(1e3 * t, 2)}
 
 
 def bench_lstsq(tq, torch, np):
@@ -472,14 +553,14 @@ def bench_lstsq(tq, torch, np):
 
 
 def bench_cholqr(tq, torch, np):
-    """TSQR against CholeskyQR and CholeskyQR2 (the comparison of Sec. 2.3)
-    on 2^20 x 64 FP64: the step's matrix (cond 1e8, seeds 2, 3) and a
-    Gaussian one (seed 2).  TSQR = factor + form Q on a copy refilled before
-    each call; CholeskyQR reads A and writes Q.  Median of 10 calls each, with
-    the orthogonality ||Q^T Q - I||_F of the result (null where the Cholesky
-    factorisation broke down)."""
+    """TSQR against CholeskyQR, CholeskyQR2 and modified Gram-Schmidt (the
+    comparison of Sec. 2.3) on 2^20 x 64 FP64: the step's matrix (cond 1e8,
+    seeds 2, 3) and a Gaussian one (seed 2).  TSQR = factor + form Q on a
+    copy refilled before each call; CholeskyQR and MGS read A and write Q.
+    Median of 10 calls each, with the orthogonality ||Q^T Q - I||_F of the
+    result (null where the Cholesky factorisation broke down)."""
     import workloads
-    out = {"workload": "TSQR vs CholeskyQR / CholeskyQR2, 1048576 x 64 FP64"}
+    out = {"workload": "TSQR vs CholeskyQR / CholeskyQR2 / MGS, 1048576 x 64 FP64"}
     for name, A_np in (("cond_1e8", workloads.conditioned(1 << 20, 64, 1e8, 2, 3)),
                        ("gaussian", workloads.gaussian(1 << 20, 64, 2))):
         A0 = torch.from_numpy(A_np).cuda()
@@ -522,6 +603,8 @@ def bench_cholqr(tq, torch, np):
         for passes, key in ((1, "cholqr"), (2, "cholqr2")):
             res[key + "_ms"] = round(timed(lambda: tq.cholqr(A0, passes, out_q=Q)), 4)
             res[key + "_orthogonality"] = orth(Q)
+        res["mgs_ms"] = round(timed(lambda: tq.mgs(A0, out_q=Q)), 4)
+        res["mgs_orthogonality"] = orth(Q)
         out[name] = res
         del A0, W, Q
         torch.cuda.empty_cache()

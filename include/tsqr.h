@@ -31,6 +31,8 @@
  *    TSQR_ERR_NOMEM     device workspace allocation failed
  *    TSQR_ERR_PLAN      handle / shape mismatch
  *    TSQR_ERR_UNSUPPORTED  n > 64 for TSQR, or an unsupported option
+ *    TSQR_ERR_TIMEOUT   (tsqr_check_status only) a bounded wait inside a
+ *                       factorisation gave up; its results are invalid
  * NaN/Inf inputs are not detected; they propagate to the outputs.
  */
 #ifndef TSQR_H
@@ -50,6 +52,7 @@ extern "C" {
 #define TSQR_ERR_NOMEM 2
 #define TSQR_ERR_PLAN 3
 #define TSQR_ERR_UNSUPPORTED 4
+#define TSQR_ERR_TIMEOUT 5
 
 #define TSQR_MAX_N 64
 
@@ -73,13 +76,24 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                or when the tree is not binary or the chains do not fit,
  *                each node starts when its children are complete.  Both give
  *                the same bits; only the schedule differs (Sec. 2.1: the
- *                tree shape and order are free). */
+ *                tree shape and order are free).
+ *   max_polls  : in the panel-by-panel tree a wave waits for its children's
+ *                progress, polling at most this many times (default 2^22,
+ *                far beyond any real wait).  A wave that gives up sets the
+ *                library's status word, which tsqr_check_status reports as
+ *                TSQR_ERR_TIMEOUT, and finishes with whatever rows are in
+ *                memory, so that factorisation's results are invalid while
+ *                every kernel still ends.  Small values exist for tests of
+ *                that error path.
+ * The library reads no environment variable: these fields are the only
+ * tuning inputs. */
 #define TSQR_FLAG_TREE_LEVELWISE 1
 typedef struct tsqr_opts {
     int32_t block_rows;
     int32_t chains;
     int32_t arity;
     int32_t flags;
+    int32_t max_polls;
 } tsqr_opts;
 
 /* TSQR factorisation A = QR (Sec. 2.1).
@@ -96,6 +110,56 @@ typedef struct tsqr_opts {
  *   8 opts, 9 q_out. */
 int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
                 const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
+/* Layout the apply kernels take for k columns of B on this implicit Q
+ * (panel `panel` of a CAQR handle, whose trailing updates are Q^T products
+ * of the panel's tree; panel = 0 for a TSQR handle).  Host only, no GPU work.
+ * Returns 1 for the wide layout (n = 64 and enough workgroups: each wave
+ * applies a block's reflectors to a 16-column tile of B over all 64 rows),
+ * 0 for the narrow one (each wave owns 16 rows of a block), or -i for an
+ * invalid argument i (1 q, 2 panel, 3 k < 1).  Lets tests check which
+ * kernels a case exercises. */
+int tsqr_apply_layout(tsqr_qtree q, int64_t panel, int64_t k);
+
+/* Waits for the work enqueued on `stream` (hipStreamSynchronize), then reads
+ * and clears the status word of the current device: TSQR_ERR_TIMEOUT if a
+ * bounded wait of a factorisation on this device gave up since the last
+ * call (see tsqr_opts.max_polls; the word is shared by every stream of the
+ * device), 0 otherwise, TSQR_ERR_HIP if the synchronisation or the read
+ * failed.  Factorisations do not synchronise by themselves, so a caller that
+ * needs the guarantee calls this after them. */
+int tsqr_check_status(void* stream);
+
+/* TSQR of a batch of `batch` independent m x n matrices (m >= n >= 1,
+ * n <= 64) stored one after another: member b is rows b*m .. b*m + m - 1 of
+ * the (batch*m) x n row-major array A (a contiguous [batch][m][n] tensor
+ * when lda = n).  Each member is reduced on its own tree (Sec. 2.1; the
+ * batch is a forest): its rows are cut into the same number of chains, a
+ * power of the arity (opts.chains = chains per member; 0 picks about one
+ * chain per SIMD over the whole batch), and its R is the root of its tree.
+ *   A is OVERWRITTEN with the leaf reflectors and borrowed by the implicit Q
+ *   as for tsqr_factor.  R: device, member b's n x n factor at R + b*strideR
+ *   (ldr >= n, strideR >= n*ldr when batch > 1), or NULL.  q_out: the
+ *   batch's implicit Q, or NULL (R only).  tsqr_apply_qt, tsqr_apply_q and
+ *   tsqr_form_q then act on the stacked (batch*m) x k array, every member
+ *   with its own Q (form_q writes each member's thin Q in its rows).
+ *   1 <= batch <= 65535.  TSQR_ERR_UNSUPPORTED if opts.chains is not a power
+ *   of the arity or the members are too short for that many chains.
+ *   Argument indices for errors: 1 dtype, 2 batch, 3 m, 4 n, 5 A, 6 lda,
+ *   8 ldr, 9 strideR, 10 opts, 11 q_out. */
+int tsqr_factor_batched(int dtype, int64_t batch, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                        int64_t strideR, const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
+/* Members of an implicit Q: 1 for tsqr_factor and caqr_factor, `batch` for
+ * tsqr_factor_batched.  members: host int64.  Errors: 1 q, 2 members. */
+int tsqr_qtree_members(tsqr_qtree q, int64_t* members);
+
+/* Batched tsqr_sign_normalize: member b's R (at R + b*strideR) and the m
+ * rows of Q starting at row b*m (Q: the stacked (batch*m) x n array, or
+ * NULL) are scaled by D_b = sign(diag R_b), sign(0) = +1.
+ * Errors: 1 dtype, 2 batch, 3 m, 4 n, 6 ldq, 7 R, 8 ldr, 9 strideR. */
+int tsqr_sign_normalize_batched(int dtype, int64_t batch, int64_t m, int64_t n, void* Q, int64_t ldq, void* R,
+                                int64_t ldr, int64_t strideR, void* stream);
 
 /* B <- Q^T B for the full m x m orthogonal Q (Sec. 1: apply the stored tree
  * of Q factors; "about the same cost as the traditionally represented Q").
@@ -138,6 +202,24 @@ int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k,
  *   8 R, 9 ldr, 10 passes. */
 int tsqr_cholqr(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
                 int64_t ldr, int passes, void* stream);
+
+/* Modified Gram-Schmidt, the other fast but unstable algorithm the paper
+ * compares TSQR with (Sec. 2.3): for j = 0..n-1, r_jj = ||a_j||,
+ * q_j = a_j / r_jj, then r_jc = q_j^T a_c and a_c -= r_jc q_j for every later
+ * column c (right-looking).  Its loss of orthogonality grows in proportion
+ * to cond(A).  Provided for comparison: TSQR is the stable path.
+ *   dtype, m, n (m >= n >= 1, n <= 64), A (device, m x n, lda >= n, not
+ *   modified unless Q is A); Q: device m x n (ldq >= n), may be A itself
+ *   (ldq = lda); R: device n x n (ldr >= n), upper triangular with a
+ *   positive diagonal, zeros below it.  n + 1 streaming passes over the rows,
+ *   each inner product reduced in a fixed order (the result does not depend
+ *   on scheduling).  A rank-deficient A (a zero r_jj) is not detected: Inf or
+ *   NaN propagate.  Partial sums live in a stream-ordered allocation released
+ *   at the end of the stream work.
+ *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 Q, 7 ldq,
+ *   8 R, 9 ldr. */
+int tsqr_mgs(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+             int64_t ldr, void* stream);
 
 /* B <- Q B (reverse order of tsqr_apply_qt).  Same arguments. */
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);

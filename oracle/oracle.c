@@ -174,7 +174,9 @@ int oracle_geqrf(int64_t m, int64_t n, double *A, double *tau)
 }
 
 /* Apply H_j = I - tau_j v_j v_j^T for j in order (first..last step dir) to the
- * m x k row-major B, where v_j comes from the geqrf output YR (m x n). */
+ * m x k row-major B, where v_j comes from the geqrf output YR (m x n).  The
+ * k columns of B are independent and are shared among OpenMP threads; each
+ * column's arithmetic is the same whatever the thread count. */
 static int apply_reflectors(int64_t m, int64_t n, int64_t k, const double *YR,
                             const double *tau, double *B, int forward)
 {
@@ -182,35 +184,47 @@ static int apply_reflectors(int64_t m, int64_t n, int64_t k, const double *YR,
         return -1;
     double *bc = to_cm(m, k, B);
     double *yc = to_cm(m, n, YR);
-    scratch_t s = {0, 0};
-    if (!bc || !yc || scratch_reserve(&s, m) != 0) {
+    if (!bc || !yc) {
         free(bc);
         free(yc);
-        free(s.p);
         return -2;
     }
-    for (int64_t step = 0; step < n; ++step) {
-        int64_t j = forward ? step : n - 1 - step;
-        if (tau[j] == 0.0)
-            continue;
-        const double *v = yc + j * m + j; /* v(0)=1 implicit, v(1:) stored */
-        int64_t len = m - j;
-        for (int64_t c = 0; c < k; ++c) {
-            double *b = bc + c * m + j;
-            s.p[0] = b[0];
-            for (int64_t i = 1; i < len; ++i)
-                s.p[i] = v[i] * b[i];
-            double tw = tau[j] * psum(s.p, len);
-            b[0] -= tw;
-            for (int64_t i = 1; i < len; ++i)
-                b[i] -= tw * v[i];
+    int fail = 0;
+#pragma omp parallel if (k > 1 && m * n > 65536)
+    {
+        scratch_t s = {0, 0};
+        int ok = scratch_reserve(&s, m) == 0;
+        if (!ok) {
+#pragma omp atomic write
+            fail = 1;
         }
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < k; ++c) {
+            if (!ok)
+                continue;
+            for (int64_t step = 0; step < n; ++step) {
+                int64_t j = forward ? step : n - 1 - step;
+                if (tau[j] == 0.0)
+                    continue;
+                const double *v = yc + j * m + j; /* v(0)=1 implicit, v(1:) stored */
+                int64_t len = m - j;
+                double *b = bc + c * m + j;
+                s.p[0] = b[0];
+                for (int64_t i = 1; i < len; ++i)
+                    s.p[i] = v[i] * b[i];
+                double tw = tau[j] * psum(s.p, len);
+                b[0] -= tw;
+                for (int64_t i = 1; i < len; ++i)
+                    b[i] -= tw * v[i];
+            }
+        }
+        free(s.p);
     }
-    from_cm(m, k, bc, B);
+    if (!fail)
+        from_cm(m, k, bc, B);
     free(bc);
     free(yc);
-    free(s.p);
-    return 0;
+    return fail ? -2 : 0;
 }
 
 /* B (m x k) <- Q^T B, Q = H_0 H_1 ... H_{n-1} (so Q^T applies H_0 first). */

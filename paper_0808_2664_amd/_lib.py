@@ -19,13 +19,15 @@ TSQR_ERR_HIP = 1
 TSQR_ERR_NOMEM = 2
 TSQR_ERR_PLAN = 3
 TSQR_ERR_UNSUPPORTED = 4
+TSQR_ERR_TIMEOUT = 5
 TSQR_MAX_N = 64
 TSQR_FLAG_TREE_LEVELWISE = 1
 
 
 class TsqrOpts(ctypes.Structure):
     _fields_ = [("block_rows", ctypes.c_int32), ("chains", ctypes.c_int32),
-                ("arity", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("arity", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("max_polls", ctypes.c_int32)]
 
 
 class TsqrError(RuntimeError):
@@ -66,12 +68,18 @@ def load():
         "tsqr_apply_q": [vp, i64, vp, i64, vp],
         "tsqr_lstsq": [i32, i64, i64, vp, i64, i64, vp, i64, vp, popts, vp],
         "tsqr_cholqr": [i32, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp],
+        "tsqr_mgs": [i32, i64, i64, vp, i64, vp, i64, vp, i64, vp],
         "tsqr_form_q": [vp, vp, i64, vp],
         "tsqr_qtree_destroy": [vp],
         "tsqr_qtree_info": [vp, p64],
         "tsqr_plan_geometry": [i64, i64, popts, p64],
         "tsqr_sign_normalize": [i32, i64, i64, vp, i64, vp, i64, vp],
         "tsqr_last_hip_error": [],
+        "tsqr_check_status": [vp],
+        "tsqr_apply_layout": [vp, i64, i64],
+        "tsqr_factor_batched": [i32, i64, i64, i64, vp, i64, vp, i64, i64, popts, ctypes.POINTER(vp), vp],
+        "tsqr_qtree_members": [vp, p64],
+        "tsqr_sign_normalize_batched": [i32, i64, i64, i64, vp, i64, vp, i64, i64, vp],
         "tsqr_set_phase_events": [i32, vp, vp],
         "caqr_factor": [i32, i64, i64, vp, i64, i64, i32, popts, ctypes.POINTER(vp), vp],
         "tsqr_copy_r": [i32, i64, vp, i64, vp, i64, vp],
@@ -97,5 +105,5 @@ def check(func: str, code: int):
         raise TsqrError(func, code, load().tsqr_last_hip_error())
 
 
-def opts(block_rows: int = 0, chains: int = 0, arity: int = 0, flags: int = 0):
-    return TsqrOpts(block_rows, chains, arity, flags)
+def opts(block_rows: int = 0, chains: int = 0, arity: int = 0, flags: int = 0, max_polls: int = 0):
+    return TsqrOpts(block_rows, chains, arity, flags, max_polls)

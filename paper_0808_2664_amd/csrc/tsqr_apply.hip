@@ -13,7 +13,11 @@
 // their submatrices in an embarrassingly parallel fashion", then the tree
 // pairs exchanging only b rows).  The two products are dense contractions
 // and run on the MFMA units (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4);
-// FP32 compute with FP64 storage is the mixed-precision CAQR update.
+// FP32 compute with FP64 storage is the mixed-precision CAQR update: the
+// products take FP32 operands (the FP64 values rounded) and accumulate in
+// FP32 from zero, and each product is then added to the FP64 values of the
+// slab and of B, which stay FP64 throughout (only Q^T is offered in this
+// form; it is the trailing update).
 //
 // Workgroup = 4 waves, each owning 16 rows of a 64-row block; 16 columns of B
 // per workgroup.  Workgroups are numbered so that all column tiles of one
@@ -32,6 +36,19 @@ using namespace dev;
 template <typename C>
 __device__ __forceinline__ C vunit(C x, int r, int c) {
     return (r > c) ? x : ((r == c) ? C(1) : C(0));
+}
+
+// FP32 products on FP64 storage (S != C): products start from zero and are
+// added to the storage-type values afterwards; with S == C the product
+// accumulates onto the values directly (one rounding fewer, same as before).
+template <typename S, typename C>
+constexpr bool kMixed = !std::is_same<S, C>::value;
+// accumulator-shaped storage of the slab in the storage type
+template <typename S, typename C>
+using SAcc = typename Mfma<typename std::conditional<std::is_same<S, C>::value, C, S>::type>::acc;
+template <typename To, typename From>
+__device__ __forceinline__ To vcvt(From v) {
+    return __builtin_convertvector(v, To);
 }
 
 // ---------------------------------------------------------------- 64-row blocks
@@ -100,7 +117,7 @@ __device__ __forceinline__ void apply64_load(Apply64Regs<S, C, NP, MODE>& R, int
 
 template <typename S, typename C, int NP, int MODE>
 __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64Regs<S, C, NP, MODE>& R,
-                                              C (&sl)[4], int wv, int l16, int l4, int n, S* __restrict__ B,
+                                              S (&sl)[4], int wv, int l16, int l4, int n, S* __restrict__ B,
                                               int64_t ldb, int64_t r0, int rows, bool top, int64_t col, bool colok) {
     typedef Mfma<C> M;
     typedef typename M::acc acc_t;
@@ -110,7 +127,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * wv + M::orow(l4, i);
-            if (r < n) R.x[i] = (S)sl[i];
+            if (r < n) R.x[i] = sl[i];
         }
     }
     // Explicit Q, blocks past the first: the block's rows of B are zero, so
@@ -118,7 +135,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
     if (MODE == MODE_FORMQ && !top) {
         if (wv < NP) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sm.part[0][wv][r][lane] = sl[r];
+            for (int r = 0; r < 4; ++r) sm.part[0][wv][r][lane] = (C)sl[r];
         }
         __syncthreads();
     } else {
@@ -146,7 +163,7 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
             C v = sm.part[0][wv][r][lane] + sm.part[1][wv][r][lane];
             v += sm.part[2][wv][r][lane];
             v += sm.part[3][wv][r][lane];
-            if (!top) v += sl[r];
+            if (!top) v += (C)sl[r];
             sm.part[0][wv][r][lane] = v;
         }
     }
@@ -165,13 +182,13 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             sm.wp[wv][r][lane] = nw[r];
-            if (!top) sl[r] += nw[r];
+            if (!top) sl[r] += (S)nw[r];
         }
     }
     __syncthreads();
     // 4. X -= Y W'
     {
-        acc_t u = acc_t{(C)R.x[0], (C)R.x[1], (C)R.x[2], (C)R.x[3]};
+        acc_t u = kMixed<S, C> ? acc_t{0, 0, 0, 0} : acc_t{(C)R.x[0], (C)R.x[1], (C)R.x[2], (C)R.x[3]};
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -189,8 +206,9 @@ __device__ __forceinline__ void apply64_block(Apply64Smem<S, C, NP>& sm, Apply64
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * wv + M::orow(l4, i);
-            if (MODE == MODE_QT && top && wv < NP && r < n) sl[i] = u[i];
-            if (r < rows && colok) B[(r0 + r) * ldb + col] = (S)u[i];
+            const S o = kMixed<S, C> ? R.x[i] + (S)u[i] : (S)u[i];
+            if (MODE == MODE_QT && top && wv < NP && r < n) sl[i] = o;
+            if (r < rows && colok) B[(r0 + r) * ldb + col] = o;
         }
     }
 }
@@ -234,11 +252,11 @@ __global__ __launch_bounds__(256, 2) void k_qt_tree64(Geom g, int ntiles, S* __r
             if (s_old != nch - 1) return;
         }
         const int64_t sa = chain_start(g, i0);
-        C sl[4];
+        S sl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int j = 16 * wv + M::orow(l4, i);
-            sl[i] = (wv < NP && j < n && colok) ? (C)pub_load(B + (sa + j) * ldb + col) : C(0);
+            sl[i] = (wv < NP && j < n && colok) ? pub_load(B + (sa + j) * ldb + col) : S(0);
         }
         for (int t = 1; t < nch; ++t) {
             const int64_t ch = i0 + t * stride;
@@ -252,7 +270,7 @@ __global__ __launch_bounds__(256, 2) void k_qt_tree64(Geom g, int ntiles, S* __r
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int j = 16 * wv + M::orow(l4, i);
-                if (j < n && colok) pub_store(B + (sa + j) * ldb + col, (S)sl[i]);
+                if (j < n && colok) pub_store(B + (sa + j) * ldb + col, sl[i]);
             }
         }
         cur = i0;
@@ -279,11 +297,11 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
     const int nb = chain_nblocks(g, chain);
     const int64_t blk0 = chain_blk0(g, chain);
     // slab tile wv (D layout = the natural rows 16wv + orow(l4, i) of the chain's first rows)
-    C sl[4];
+    S sl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int j = 16 * wv + M::orow(l4, i);
-        sl[i] = (MODE != MODE_QT && wv < NP && j < n && colok) ? (C)B[(start + j) * ldb + col] : C(0);
+        sl[i] = (MODE != MODE_QT && wv < NP && j < n && colok) ? B[(start + j) * ldb + col] : S(0);
     }
     Apply64Regs<S, C, NP, MODE> cur, nxt;
     auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int j = 16 * wv + M::orow(l4, i);
-            if (j < n && colok) B[(start + j) * ldb + col] = (S)sl[i];
+            if (j < n && colok) B[(start + j) * ldb + col] = sl[i];
         }
     }
 }
@@ -413,21 +431,21 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         }
     };
     // slab S (the chain's first 64 rows), accumulator layout
-    acc_t sl[4];
+    SAcc<S, C> sl[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * p + M::orow(l4, i);
-            sl[p][i] = (MODE != MODE_QT && colok) ? (C)B[(start + r) * ldb + col] : C(0);
+            sl[p][i] = (MODE != MODE_QT && colok) ? B[(start + r) * ldb + col] : S(0);
         }
-    C x[16];
+    S x[16];
     stage_load(0);
     x_load(0);
     stage_store(0);
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) x[kk] = (C)xn[kk];
+    for (int kk = 0; kk < 16; ++kk) x[kk] = xn[kk];
     for (int bi = 0; bi < nb; ++bi) {
         const int b = blk(bi);
         const bool top = b == 0;
@@ -450,12 +468,15 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         // W = V^T [S; X]
         acc_t w[4];
         const bool xzero = (MODE == MODE_FORMQ) && !top;
+        C xc[16];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) xc[kk] = (C)x[kk];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            w[p] = top ? acc_t{0, 0, 0, 0} : sl[p];
+            w[p] = top ? acc_t{0, 0, 0, 0} : vcvt<acc_t>(sl[p]);
             if (!xzero) {
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+                for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], xc[kk], w[p]);
             }
         }
         // W' = T^T W (Q^T) or T W (Q); kept negated
@@ -479,7 +500,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         // S -= W'
         if (!top) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+            for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
         }
         if (!early && more) {
             stage_load(bi + 1);
@@ -488,13 +509,13 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         // X -= Y W'
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+            acc_t u = kMixed<S, C> ? acc_t{0, 0, 0, 0} : acc_t{xc[4 * r], xc[4 * r + 1], xc[4 * r + 2], xc[4 * r + 3]};
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int kc = 0; kc < 4; ++kc) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+            for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? x[4 * r + i] + (S)u[i] : (S)u[i];
         }
         if (MODE == MODE_QT && top) {
             // the chain's first block becomes the slab
@@ -508,7 +529,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
                 const int r = xrow(kk);
-                if (r < rows && colok) B[(r0 + r) * ldb + col] = (S)x[kk];
+                if (r < rows && colok) B[(r0 + r) * ldb + col] = x[kk];
             }
         }
         if (more) {
@@ -516,14 +537,14 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             stage_store(bi + 1);
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) x[kk] = (C)xn[kk];
+            for (int kk = 0; kk < 16; ++kk) x[kk] = xn[kk];
         }
     }
     if (MODE == MODE_QT && colok) {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) B[(start + 16 * p + M::orow(l4, i)) * ldb + col] = (S)sl[p][i];
+            for (int i = 0; i < 4; ++i) B[(start + 16 * p + M::orow(l4, i)) * ldb + col] = sl[p][i];
     }
 }
 
@@ -568,12 +589,12 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
             if (s_old != nch - 1) return;
         }
         const int64_t sa = chain_start(g, i0);
-        acc_t sl[4];
+        SAcc<S, C> sl[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                sl[p][i] = colok ? (C)pub_load(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col) : C(0);
+                sl[p][i] = colok ? pub_load(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col) : S(0);
         for (int t = 1; t < nch; ++t) {
             const int64_t ch = i0 + t * stride;
             S* Bc = B + chain_start(g, (int)ch) * ldb;
@@ -588,9 +609,9 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
                 const int e = tid + NT * u;
                 ts[u] = (e < W_TRI) ? Tc[e] : S(0);
             }
-            C x[16];
+            S x[16];
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) x[kk] = colok ? (C)pub_load(Bc + xrow(kk) * ldb + col) : C(0);
+            for (int kk = 0; kk < 16; ++kk) x[kk] = colok ? pub_load(Bc + xrow(kk) * ldb + col) : S(0);
             if (staged) __syncthreads();  // every wave is done with the previous step's operands
 #pragma unroll
             for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
@@ -605,10 +626,10 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
             acc_t w[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                w[p] = sl[p];
+                w[p] = vcvt<acc_t>(sl[p]);
 #pragma unroll
                 for (int kk = 0; kk < 16; ++kk)
-                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], (C)x[kk], w[p]);
             }
             acc_t nw[4];
 #pragma unroll
@@ -625,21 +646,22 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
                     }
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+            for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+                acc_t u = kMixed<S, C> ? acc_t{0, 0, 0, 0}
+                                       : acc_t{(C)x[4 * r], (C)x[4 * r + 1], (C)x[4 * r + 2], (C)x[4 * r + 3]};
 #pragma unroll
                 for (int p = 0; p < 4; ++p)
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc)
                         if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+                for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? x[4 * r + i] + (S)u[i] : (S)u[i];
             }
             if (colok) {
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = (S)x[kk];
+                for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = x[kk];
             }
         }
         if (colok) {
@@ -675,11 +697,11 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
     if (nch > g.arity) nch = g.arity;
     if (nch <= 1) return;
     const int64_t sa = chain_start(g, (int)i0);
-    acc_t sl[4];
+    SAcc<S, C> sl[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sl[p][i] = colok ? (C)B[(sa + 16 * p + M::orow(l4, i)) * ldb + col] : C(0);
+        for (int i = 0; i < 4; ++i) sl[p][i] = colok ? B[(sa + 16 * p + M::orow(l4, i)) * ldb + col] : S(0);
     bool staged = false;
     for (int t = nch - 1; t >= 1; --t) {
         const int64_t ch = i0 + t * stride;
@@ -694,9 +716,9 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
             const int e = tid + NT * u;
             ts[u] = (e < W_TRI) ? Tc[e] : S(0);
         }
-        C x[16];
+        S x[16];
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) x[kk] = (MODE != MODE_FORMQ && colok) ? (C)Bc[xrow(kk) * ldb + col] : C(0);
+        for (int kk = 0; kk < 16; ++kk) x[kk] = (MODE != MODE_FORMQ && colok) ? Bc[xrow(kk) * ldb + col] : S(0);
         if (staged) __syncthreads();  // every wave is done with the previous step's operands
 #pragma unroll
         for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
@@ -711,11 +733,11 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
         acc_t w[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            w[p] = sl[p];
+            w[p] = vcvt<acc_t>(sl[p]);
             if (MODE != MODE_FORMQ) {
 #pragma unroll
                 for (int kk = 0; kk < 16; ++kk)
-                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], x[kk], w[p]);
+                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], (C)x[kk], w[p]);
             }
         }
         acc_t nw[4];
@@ -733,21 +755,22 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
                 }
         }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) sl[p] += nw[p];
+        for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            acc_t u = acc_t{x[4 * r], x[4 * r + 1], x[4 * r + 2], x[4 * r + 3]};
+            acc_t u = kMixed<S, C> ? acc_t{0, 0, 0, 0}
+                                       : acc_t{(C)x[4 * r], (C)x[4 * r + 1], (C)x[4 * r + 2], (C)x[4 * r + 3]};
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int kc = 0; kc < 4; ++kc)
                     if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x[4 * r + i] = u[i];
+            for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? x[4 * r + i] + (S)u[i] : (S)u[i];
         }
         if (colok) {
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = (S)x[kk];
+            for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = x[kk];
         }
     }
     if (colok) {
@@ -764,11 +787,11 @@ __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
 }
 
 template <typename T>
-__global__ void k_init_formq(int64_t n, T* __restrict__ Q, int64_t ldq) {
+__global__ void k_init_formq(int64_t n, int64_t mb, T* __restrict__ Q, int64_t ldq) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     const int64_t i = e / n, j = e - i * n;
-    Q[i * ldq + j] = (i == j) ? T(1) : T(0);
+    Q[((int64_t)blockIdx.y * mb + i) * ldq + j] = (i == j) ? T(1) : T(0);
 }
 
 // Layout of an apply with n = 64: the wide kernels (a 16-column tile over all
@@ -781,6 +804,8 @@ static bool use_wide(const Geom& g, int64_t k) {
     const int64_t tw = k <= 32 ? 2 : 4;
     return (int64_t)g.W * ((k + 16 * tw - 1) / (16 * tw)) >= 256;
 }
+
+bool apply_wide(const Geom& g, int64_t k) { return use_wide(g, k); }
 
 template <typename S, typename C, int NC, int H, int MODE>
 static hipError_t chain_apply_launch(const Geom& g, const S* Y, int64_t ldy, const Work& wk, S* B, int64_t ldb,
@@ -864,11 +889,11 @@ __global__ __launch_bounds__(256, 2) void k_node_apply64(Geom g, int lev, int nt
     if (nch > g.arity) nch = g.arity;
     if (nch <= 1) return;
     const int64_t sa = chain_start(g, (int)i0);
-    C sl[4];
+    S sl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int j = 16 * wv + M::orow(l4, i);
-        sl[i] = (wv < NP && j < n && colok) ? (C)B[(sa + j) * ldb + col] : C(0);
+        sl[i] = (wv < NP && j < n && colok) ? B[(sa + j) * ldb + col] : S(0);
     }
     for (int t = nch - 1; t >= 1; --t) {
         const int64_t ch = i0 + t * stride;
@@ -882,7 +907,7 @@ __global__ __launch_bounds__(256, 2) void k_node_apply64(Geom g, int lev, int nt
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int j = 16 * wv + M::orow(l4, i);
-            if (j < n && colok) B[(sa + j) * ldb + col] = (S)sl[i];
+            if (j < n && colok) B[(sa + j) * ldb + col] = sl[i];
         }
     }
 }
@@ -940,11 +965,17 @@ static hipError_t apply_mode(const Geom& g, const S* Y, int64_t ldy, const Work&
 template <typename S, typename C, int NC>
 static hipError_t apply_nc(const Geom& g, const S* Y, int64_t ldy, const Work& wk, S* B, int64_t ldb, int64_t k,
                            int mode, hipStream_t st) {
-    switch (mode) {
-        case MODE_QT: return apply_mode<S, C, NC, MODE_QT>(g, Y, ldy, wk, B, ldb, k, st);
-        case MODE_Q: return apply_mode<S, C, NC, MODE_Q>(g, Y, ldy, wk, B, ldb, k, st);
-        case MODE_FORMQ: return apply_mode<S, C, NC, MODE_FORMQ>(g, Y, ldy, wk, B, ldb, k, st);
-        default: return hipErrorInvalidValue;
+    if constexpr (kMixed<S, C>) {
+        // FP32 products on FP64 storage: the trailing update (Q^T) only
+        if (mode != MODE_QT) return hipErrorInvalidValue;
+        return apply_mode<S, C, NC, MODE_QT>(g, Y, ldy, wk, B, ldb, k, st);
+    } else {
+        switch (mode) {
+            case MODE_QT: return apply_mode<S, C, NC, MODE_QT>(g, Y, ldy, wk, B, ldb, k, st);
+            case MODE_Q: return apply_mode<S, C, NC, MODE_Q>(g, Y, ldy, wk, B, ldb, k, st);
+            case MODE_FORMQ: return apply_mode<S, C, NC, MODE_FORMQ>(g, Y, ldy, wk, B, ldb, k, st);
+            default: return hipErrorInvalidValue;
+        }
     }
 }
 
@@ -986,10 +1017,11 @@ hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st) {
-    const int nb = (int)((n * n + 255) / 256);
-    if (f64) k_init_formq<double><<<nb, 256, 0, st>>>(n, (double*)Q, ldq);
-    else k_init_formq<float><<<nb, 256, 0, st>>>(n, (float*)Q, ldq);
+hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, hipStream_t st) {
+    if (members < 1 || members > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n * n + 255) / 256), (unsigned)members);
+    if (f64) k_init_formq<double><<<grid, 256, 0, st>>>(n, mb, (double*)Q, ldq);
+    else k_init_formq<float><<<grid, 256, 0, st>>>(n, mb, (float*)Q, ldq);
     return hipGetLastError();
 }
 

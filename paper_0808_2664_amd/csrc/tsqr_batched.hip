@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64, OCC) void k_batch_tsqr(const BMat* __restrict__
         if (it >= nitems) break;
         const BItem bi = items[it];
         const BMat bm = mats[bi.mat];
-        TreeArgs ta{bm.cnt, (void*)R[bi.mat], ldr[bi.mat], 1};
+        TreeArgs ta{bm.cnt, (void*)R[bi.mat], ldr[bi.mat], 1, 0, nullptr, 0};  // no bounded waits (node by node)
         wave_tsqr<T, NP, 4, false, false>(sm, bm.g, bi.chain, A[bi.mat], lda[bi.mat], (T*)bm.tau_blk, (T*)bm.T_blk, (T*)bm.Rbuf,
                             (T*)bm.Ynode, (T*)bm.Tnode, (T*)bm.tau_node, ta);
     }

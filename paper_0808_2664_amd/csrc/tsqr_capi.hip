@@ -22,6 +22,7 @@ struct tsqr_qtree_s {
     // CAQR: one TSQR tree per panel, panel p acting on rows/cols p*panel..
     std::vector<tsqr_qtree_s*> panels;
     int64_t m = 0, n = 0, panel = 0;
+    int64_t members = 1;  // batched TSQR: independent stacked matrices of m / members rows
 };
 
 static thread_local int g_last_hip = 0;
@@ -35,13 +36,31 @@ static int hip_fail(hipError_t e) {
     return e == hipErrorOutOfMemory ? TSQR_ERR_NOMEM : TSQR_ERR_HIP;
 }
 
-static int env_int(const char* name, int dflt) {
-    const char* s = getenv(name);
-    if (!s || !*s) return dflt;
-    return atoi(s);
-}
+// The library's status word (bit 0: a bounded wait of the pipelined tree
+// gave up); each device holds its own copy.  Kernels receive its device
+// address as an argument; the host side obtains that address once per device.
+static __device__ __align__(256) int g_status;
 
 namespace tsqr {
+
+int record_hip_error(hipError_t e) { return hip_fail(e); }
+
+int* status_word() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    static int* addr[64];
+    static bool done[64];
+    if (!done[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_status)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        addr[dev] = (int*)p;
+        done[dev] = true;
+    }
+    return addr[dev];
+}
 
 int padded_nc(int64_t n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64; }
 
@@ -55,7 +74,7 @@ constexpr int64_t kDefaultChains = 1024;
 int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g);
 
 int make_geom_opts(int64_t m, int64_t n, const GeomOpts& go, Geom* g) {
-    tsqr_opts o{go.block_rows, go.chains, go.arity, go.flags};
+    tsqr_opts o{go.block_rows, go.chains, go.arity, go.flags, 0};
     return make_geom(m, n, &o, g);
 }
 
@@ -63,9 +82,9 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     if (n < 1 || n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     if (m < n) return -1;
     const int NC = padded_nc(n);
-    int h = (o && o->block_rows) ? o->block_rows : env_int("TSQR_BLOCK_ROWS", wave_default_h(NC));
-    int chains = (o && o->chains) ? o->chains : env_int("TSQR_CHAINS", 0);
-    int arity = (o && o->arity) ? o->arity : env_int("TSQR_ARITY", 2);
+    int h = (o && o->block_rows) ? o->block_rows : wave_default_h(NC);
+    int chains = (o && o->chains) ? o->chains : 0;
+    int arity = (o && o->arity) ? o->arity : 2;
     const int flags = o ? o->flags : 0;
     if (flags & ~TSQR_FLAG_TREE_LEVELWISE) return TSQR_ERR_UNSUPPORTED;
     if (!wave_shape_ok(NC, h)) return TSQR_ERR_UNSUPPORTED;
@@ -96,7 +115,52 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     g->nblocks = (W - 1) * (S / h) + (last + h - 1) / h;
     g->NC = padded_nc(n);
     g->flags = (flags & TSQR_FLAG_TREE_LEVELWISE) ? TREE_LEVELWISE : 0;
+    g->mb = m;
+    g->cpm = (int)W;
+    g->bpm = g->nblocks;
     return 0;
+}
+
+// Forest geometry of `batch` stacked matrices of mb rows (Geom::mb): each
+// member is cut into the same cpm chains and reduced by its own tree of
+// arity a, so cpm must be a power of a and the one-member geometry must have
+// exactly cpm chains.  chains (opts) = chains per member; 0 picks the largest
+// such power of a that gives about `target` chains in all.
+int make_geom_batch(int64_t batch, int64_t mb, int64_t n, const tsqr_opts* o, int64_t target, Geom* g) {
+    if (batch < 1) return -2;
+    const int arity = (o && o->arity) ? o->arity : 2;
+    if (arity < 2) return TSQR_ERR_UNSUPPORTED;
+    int64_t cpm = 1;
+    if (o && o->chains) {
+        cpm = o->chains;
+    } else {
+        while (cpm * arity * batch <= target) cpm *= arity;
+    }
+    for (;;) {
+        int64_t p = 1;
+        while (p < cpm) p *= arity;
+        if (p != cpm) return TSQR_ERR_UNSUPPORTED;  // not a power of the arity
+        tsqr_opts o1 = o ? *o : tsqr_opts{0, 0, 0, 0, 0};
+        o1.chains = (int32_t)cpm;
+        o1.arity = arity;
+        Geom g1;
+        int rc = make_geom(mb, n, &o1, &g1);
+        if (rc != 0) return rc;
+        if (g1.W == cpm) {
+            if (batch * cpm > 0x7fffffff || batch * mb < mb) return TSQR_ERR_UNSUPPORTED;
+            *g = g1;
+            g->m = batch * mb;
+            g->W = (int)(batch * cpm);
+            g->nblocks = batch * g1.nblocks;
+            g->mb = mb;
+            g->cpm = (int)cpm;
+            g->bpm = g1.nblocks;
+            return 0;
+        }
+        // fewer chains than asked for (short member): a smaller power
+        if ((o && o->chains) || cpm == 1) return TSQR_ERR_UNSUPPORTED;
+        cpm /= arity;
+    }
 }
 
 // Elements of one chain's published R: its packed upper triangle (rows of
@@ -144,12 +208,21 @@ static int check_dtype(int dtype) { return dtype == TSQR_F32 || dtype == TSQR_F6
 
 // TSQR of a device matrix into a fresh handle (shared by tsqr_factor and the
 // CAQR panels).  R: optional; r_upper_only keeps what is below R's diagonal.
+static int factor_geom(int dtype, const Geom& g, void* A, int64_t lda, void* R, int64_t ldr, int64_t rstride,
+                       bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st, bool want_q);
+
 static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
                        bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st,
                        bool want_q = true) {
     Geom g;
     int rc = tsqr::make_geom(m, n, opts, &g);
     if (rc != 0) return rc;
+    return factor_geom(dtype, g, A, lda, R, ldr, 0, r_upper_only, opts, out, st, want_q);
+}
+
+static int factor_geom(int dtype, const Geom& g, void* A, int64_t lda, void* R, int64_t ldr, int64_t rstride,
+                       bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st, bool want_q) {
+    const int64_t m = g.m, n = g.n;
     const bool f64 = dtype == TSQR_F64;
     tsqr_qtree_s* q = new tsqr_qtree_s();
     q->kind = 0;
@@ -160,6 +233,7 @@ static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, vo
     q->stream = st;
     q->m = m;
     q->n = n;
+    q->members = g.m / g.mb;
     q->wk.bytes = tsqr::work_bytes(g, f64);
     hipError_t e = hipMallocAsync(&q->wk.base, q->wk.bytes, st);
     if (e != hipSuccess) {
@@ -167,7 +241,8 @@ static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, vo
         return hip_fail(e);
     }
     tsqr::work_carve(&q->wk, g, f64);
-    e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, !r_upper_only, want_q, st);
+    e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, rstride, !r_upper_only, want_q, opts ? opts->max_polls : 0,
+                            st);
     if (e != hipSuccess) {
         (void)hipFreeAsync(q->wk.base, st);
         delete q;
@@ -202,6 +277,31 @@ int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, 
     tsqr_qtree_s* q = nullptr;
     int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream, q_out != nullptr);
     if (rc != 0) return rc == -1 ? -2 : rc;
+    if (q_out) *q_out = q;
+    else destroy_impl(q);
+    return 0;
+}
+
+int tsqr_factor_batched(int dtype, int64_t batch, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                        int64_t strideR, const tsqr_opts* opts, tsqr_qtree* q_out, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (batch < 1 || batch > 65535) return -2;
+    if (m < 1) return -3;
+    if (n < 1 || n > m) return n > m ? -3 : -4;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -5;
+    if (lda < n) return -6;
+    if (R && ldr < n) return -8;
+    if (R && batch > 1 && strideR < n * ldr) return -9;
+    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -10;
+    if (!R && !q_out) return -11;
+    Geom g;
+    // about one chain per SIMD (two for FP32, whose factor kernel fits two waves)
+    int rc = tsqr::make_geom_batch(batch, m, n, opts, dtype == TSQR_F64 ? 1024 : 2048, &g);
+    if (rc != 0) return rc == -1 ? -3 : rc;
+    tsqr_qtree_s* q = nullptr;
+    rc = factor_geom(dtype, g, A, lda, R, ldr, strideR, false, opts, &q, (hipStream_t)stream, q_out != nullptr);
+    if (rc != 0) return rc;
     if (q_out) *q_out = q;
     else destroy_impl(q);
     return 0;
@@ -293,6 +393,22 @@ int tsqr_cholqr(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, voi
     return e == hipSuccess ? 0 : hip_fail(e);
 }
 
+int tsqr_mgs(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+             int64_t ldr, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!Q) return -6;
+    if (ldq < n || (Q == A && ldq != lda)) return -7;
+    if (!R) return -8;
+    if (ldr < n) return -9;
+    hipError_t e = tsqr::launch_mgs(dtype == TSQR_F64, m, n, A, lda, Q, ldq, R, ldr, (hipStream_t)stream);
+    return e == hipSuccess ? 0 : hip_fail(e);
+}
+
 int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream) {
     if (!q) return -1;
     if (k < 0) return -2;
@@ -313,7 +429,7 @@ int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
         if (e != hipSuccess) return hip_fail(e);
         return apply_impl(q, q->n, Q, ldq, tsqr::MODE_Q, st);
     }
-    hipError_t e = tsqr::launch_init_formq(q->f64, q->n, Q, ldq, st);
+    hipError_t e = tsqr::launch_init_formq(q->f64, q->members, q->m / q->members, q->n, Q, ldq, st);
     if (e != hipSuccess) return hip_fail(e);
     return apply_one(q, q->n, Q, ldq, tsqr::MODE_FORMQ, q->f64, st);
 }
@@ -354,7 +470,6 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // hides only behind a long enough update): eight blocks for panels of
     // 12288 rows or more, four below (measured on 8192^2 and 16384^2), node
     // by node (no waiting on a stream shared with the update).
-    const int chain_blocks_env = env_int("TSQR_CAQR_CHAIN_BLOCKS", 0);
     hipStream_t s2 = nullptr;
     hipEvent_t ev_head = nullptr, ev_fact = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
@@ -366,7 +481,7 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         if (s2) (void)hipStreamDestroy(s2);
     };
     auto panel_opts = [&](int64_t rows) {
-        tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0};
+        tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0, 0};
         if (o.chains == 0) {
             const int64_t blocks = (rows + 63) / 64;
             // eight-block chains halve the update's tree steps against four;
@@ -374,9 +489,7 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
             // critical path near the end) stays short, except with the FP32
             // update on matrices of 12288 columns or more, where eight is
             // faster for every panel (measured at 8192, 12288 and 16384)
-            const int chain_blocks = chain_blocks_env > 0
-                                         ? chain_blocks_env
-                                         : ((rows >= 12288 || (!cf64 && n >= 12288)) ? 8 : 4);
+            const int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288)) ? 8 : 4;
             const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
         }
@@ -448,6 +561,26 @@ int tsqr_qtree_info(tsqr_qtree q, int64_t* info) {
     return 0;
 }
 
+int tsqr_qtree_members(tsqr_qtree q, int64_t* members) {
+    if (!q) return -1;
+    if (!members) return -2;
+    *members = q->members;
+    return 0;
+}
+
+int tsqr_apply_layout(tsqr_qtree q, int64_t panel, int64_t k) {
+    if (!q) return -1;
+    const tsqr_qtree_s* t = q;
+    if (q->kind == 1) {
+        if (panel < 0 || panel >= (int64_t)q->panels.size()) return -2;
+        t = q->panels[(size_t)panel];
+    } else if (panel != 0) {
+        return -2;
+    }
+    if (k < 1) return -3;
+    return tsqr::apply_wide(t->g, k) ? 1 : 0;
+}
+
 int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out) {
     if (m < 1) return -1;
     if (n < 1 || n > m) return n > m ? -1 : -2;
@@ -503,6 +636,21 @@ int tsqr_backward(int dtype, int64_t batch, int64_t m, int64_t n, const void* Q,
 
 int tsqr_last_hip_error(void) { return g_last_hip; }
 
+int tsqr_check_status(void* stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    int* w = tsqr::status_word();
+    if (!w) return hip_fail(hipErrorInvalidSymbol);
+    int v = 0;
+    e = hipMemcpy(&v, w, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    if (v != 0) {
+        e = hipMemset(w, 0, sizeof(int));
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return (v & 1) ? TSQR_ERR_TIMEOUT : 0;
+}
+
 int tsqr_set_phase_events(int phase, void* start, void* stop) {
     if (phase < 0 || phase >= tsqr::NPHASE) return -1;
     tsqr::g_phase.start[phase] = (hipEvent_t)start;
@@ -517,6 +665,7 @@ const char* tsqr_status_string(int status) {
         case TSQR_ERR_NOMEM: return "device memory allocation failed";
         case TSQR_ERR_PLAN: return "handle or shape mismatch";
         case TSQR_ERR_UNSUPPORTED: return "unsupported size or option";
+        case TSQR_ERR_TIMEOUT: return "a bounded wait inside a factorisation gave up; its results are invalid";
         default: return status < 0 ? "invalid argument" : "unknown status";
     }
 }
@@ -544,6 +693,55 @@ __global__ void k_sign_normalize_r(int64_t n, T* __restrict__ R, int64_t ldr) {
     const T d = (R[i * ldr + i] < T(0)) ? T(-1) : T(1);
     __syncthreads();
     for (int64_t j = i + threadIdx.x; j < n; j += blockDim.x) R[i * ldr + j] *= d;
+}
+
+template <typename T>
+__global__ void k_sign_normalize_b(int64_t mb, int64_t n, T* __restrict__ Q, int64_t ldq, const T* __restrict__ R,
+                                   int64_t ldr, int64_t sr) {
+    // Q of member blockIdx.y: column j scaled by the sign of its R_jj
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mb * n) return;
+    const int64_t i = e / n, j = e - i * n, b = blockIdx.y;
+    const T* Rb = R + b * sr;
+    if (Rb[j * ldr + j] < T(0)) Q[(b * mb + i) * ldq + j] = -Q[(b * mb + i) * ldq + j];
+}
+
+template <typename T>
+__global__ void k_sign_normalize_rb(int64_t n, T* __restrict__ R, int64_t ldr, int64_t sr) {
+    // row blockIdx.x of member blockIdx.y's R scaled by the sign of its diagonal entry
+    T* Rb = R + (int64_t)blockIdx.y * sr;
+    const int64_t i = blockIdx.x;
+    const T d = (Rb[i * ldr + i] < T(0)) ? T(-1) : T(1);
+    __syncthreads();
+    for (int64_t j = i + threadIdx.x; j < n; j += blockDim.x) Rb[i * ldr + j] *= d;
+}
+
+extern "C" int tsqr_sign_normalize_batched(int dtype, int64_t batch, int64_t m, int64_t n, void* Q, int64_t ldq,
+                                           void* R, int64_t ldr, int64_t strideR, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (batch < 1 || batch > 65535) return -2;
+    if (m < 0) return -3;
+    if (n < 0 || (Q && n > m)) return -4;
+    if (Q && ldq < n) return -6;
+    if (!R) return -7;
+    if (ldr < n) return -8;
+    if (batch > 1 && strideR < n * ldr) return -9;
+    if (n == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (Q && m > 0) {
+        const dim3 grid((unsigned)((m * n + 255) / 256), (unsigned)batch);
+        if (dtype == TSQR_F64)
+            k_sign_normalize_b<double><<<grid, 256, 0, st>>>(m, n, (double*)Q, ldq, (const double*)R, ldr, strideR);
+        else
+            k_sign_normalize_b<float><<<grid, 256, 0, st>>>(m, n, (float*)Q, ldq, (const float*)R, ldr, strideR);
+    }
+    const dim3 gr((unsigned)n, (unsigned)batch);
+    if (dtype == TSQR_F64)
+        k_sign_normalize_rb<double><<<gr, 64, 0, st>>>(n, (double*)R, ldr, strideR);
+    else
+        k_sign_normalize_rb<float><<<gr, 64, 0, st>>>(n, (float*)R, ldr, strideR);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : hip_fail(e);
 }
 
 extern "C" int tsqr_sign_normalize(int dtype, int64_t m, int64_t n, void* Q, int64_t ldq, void* R, int64_t ldr,

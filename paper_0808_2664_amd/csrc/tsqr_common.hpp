@@ -24,21 +24,37 @@ struct Geom {
     int64_t nblocks = 0;  // blocks over all chains
     int NC = 0;           // padded column count: 8, 16, 32 or 64
     int flags = 0;        // TREE_LEVELWISE
+    // A batch of independent matrices of mb rows each, stacked (member b is
+    // rows b*mb .. b*mb + mb - 1), is reduced as a forest: each member has
+    // its own cpm chains (a power of the arity) and its own tree of `levels`
+    // levels, rooted at chain b*cpm.  One matrix: mb = m, cpm = W.
+    int64_t mb = 0;       // rows per member
+    int cpm = 0;          // chains per member
+    int64_t bpm = 0;      // blocks per member
 };
 
 // Geom::flags: reduce the tree node by node as children complete, never with
 // the panel-pipelined tree (the tsqr_opts flag of the same meaning).
 constexpr int TREE_LEVELWISE = 1;
 
-__host__ __device__ inline int64_t chain_start(const Geom& g, int c) { return (int64_t)c * g.S; }
+// Chain c is chain c % cpm of member c / cpm; a member's last chain takes
+// the member's remaining rows.
+__host__ __device__ inline int64_t chain_start(const Geom& g, int c) {
+    const int mem = c / g.cpm, loc = c - mem * g.cpm;
+    return (int64_t)mem * g.mb + (int64_t)loc * g.S;
+}
 __host__ __device__ inline int64_t chain_end(const Geom& g, int c) {
-    return (c == g.W - 1) ? g.m : (int64_t)(c + 1) * g.S;
+    const int mem = c / g.cpm, loc = c - mem * g.cpm;
+    return (loc == g.cpm - 1) ? (int64_t)(mem + 1) * g.mb : (int64_t)mem * g.mb + (int64_t)(loc + 1) * g.S;
 }
 __host__ __device__ inline int chain_nblocks(const Geom& g, int c) {
     int64_t len = chain_end(g, c) - chain_start(g, c);
     return (int)((len + g.h - 1) / g.h);
 }
-__host__ __device__ inline int64_t chain_blk0(const Geom& g, int c) { return (int64_t)c * (g.S / g.h); }
+__host__ __device__ inline int64_t chain_blk0(const Geom& g, int c) {
+    const int mem = c / g.cpm, loc = c - mem * g.cpm;
+    return (int64_t)mem * g.bpm + (int64_t)loc * (g.S / g.h);
+}
 
 // Tree level `lev` (1-based) with arity a: stride = a^(lev-1).  Nodes start at
 // multiples of a*stride; their children are i + t*stride, t = 1..a-1, < W.
@@ -87,12 +103,18 @@ inline void phase_end(int p, hipStream_t st) {
 // (row-major, ldr; zeros below the diagonal when zero_lower; R may be null).
 // want_q = false: only R and the leaf reflectors are produced (no implicit Q
 // is kept, so tau, T and the tree's reflectors are not formed or stored).
+// rstride: elements between the R factors of a batch's members (0 for one matrix).
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
-                         bool zero_lower, bool want_q, hipStream_t st);
+                         int64_t rstride, bool zero_lower, bool want_q, int max_polls, hipStream_t st);
 // Host-side geometry and workspace layout (tsqr_capi.hip).
 struct GeomOpts {
     int block_rows = 0, chains = 0, arity = 0, flags = 0;
 };
+// Polls of a bounded wait in the panel-pipelined tree before it gives up.
+constexpr int kDefaultMaxPolls = 1 << 22;
+// Device address of the library's status word on the current device (bit 0:
+// a bounded wait gave up), or null if it could not be obtained.
+int* status_word();
 int make_geom_opts(int64_t m, int64_t n, const GeomOpts& o, Geom* g);
 size_t work_bytes(const Geom& g, bool f64);
 void work_carve(Work* w, const Geom& g, bool f64);
@@ -104,7 +126,11 @@ hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, int64_t lds, voi
                          hipStream_t st);
 hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const void* Y, int64_t ldy,
                         const Work& wk, void* B, int64_t ldb, int64_t k, int mode, hipStream_t st);
-hipError_t launch_init_formq(bool f64, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+// [I_n; 0] at the top of every member's thin Q (the slab of each member's root chain).
+hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+// Whether launch_apply takes the wide kernels (a 16-column tile of B over all
+// 64 rows of a block per wave) for k columns on geometry g.
+bool apply_wide(const Geom& g, int64_t k);
 hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t ldq, hipStream_t st);
 // Least squares steps after Q^T B (tsqr_lstsq.hip): X = R^{-1} B(0:n, :) in
 // place, and the 2-norms of rows [r0, m) of each of the k columns of B.
@@ -115,6 +141,9 @@ hipError_t launch_colnorm(bool f64, int64_t r0, int64_t m, const void* B, int64_
 // CholeskyQR (passes = 1) or CholeskyQR2 (passes = 2) of A into Q and R.
 hipError_t launch_cholqr(bool f64, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
                          int64_t ldr, int passes, hipStream_t st);
+// Modified Gram-Schmidt of A into Q and R (n + 1 passes over the rows).
+hipError_t launch_mgs(bool f64, int64_t m, int64_t n, const void* A, int64_t lda, void* Q, int64_t ldq, void* R,
+                      int64_t ldr, hipStream_t st);
 hipError_t launch_backward(bool f64, int64_t batch, int64_t m, int64_t n, const void* Q, int64_t ldq, int64_t sq,
                            const void* R, int64_t ldr, int64_t sr, const void* dQ, int64_t lddq, int64_t sdq,
                            const void* dR, int64_t lddr, int64_t sdr, void* dA, int64_t ldda, int64_t sda,

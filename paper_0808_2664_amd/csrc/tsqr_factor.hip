@@ -72,12 +72,14 @@ static hipError_t factor_t(const Geom& g, T* A, int64_t lda, const Work& wk, con
 }
 
 hipError_t launch_factor(bool f64, const Geom& g, void* A, int64_t lda, const Work& wk, void* R, int64_t ldr,
-                         bool zero_lower, bool want_q, hipStream_t st) {
+                         int64_t rstride, bool zero_lower, bool want_q, int max_polls, hipStream_t st) {
+    int* status = status_word();
+    if (!status) return hipErrorInvalidDevice;
     const int64_t ncnt = (int64_t)g.W * (g.levels + 1);
     k_zero_i32<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(wk.cnt, ncnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    TreeArgs ta{wk.cnt, R, ldr, zero_lower ? 1 : 0};
+    TreeArgs ta{wk.cnt, R, ldr, zero_lower ? 1 : 0, max_polls > 0 ? max_polls : kDefaultMaxPolls, status, rstride};
     phase_begin(0, st);
     if (want_q)
         e = f64 ? factor_t<double, true>(g, (double*)A, lda, wk, ta, st)

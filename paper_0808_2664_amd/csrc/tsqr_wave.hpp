@@ -658,7 +658,15 @@ struct TreeArgs {
     void* Rout;      // final R (row-major, ldr), or null
     int64_t ldr;
     int zero_lower;  // also write zeros below R's diagonal
+    int max_polls;   // polls of a bounded wait before it gives up (pipelined tree)
+    int* status;     // status word: bit 0 set when a bounded wait gave up
+    int64_t rstride; // elements between the R factors of a batch's members
 };
+// Where member `mem` of a batch writes its R.
+template <typename T>
+__device__ __forceinline__ T* rout_of(const TreeArgs& ta, int mem) {
+    return (T*)ta.Rout + (int64_t)mem * ta.rstride;
+}
 
 // ---- the panel-pipelined binary tree ----------------------------------------------
 //
@@ -675,15 +683,28 @@ struct TreeArgs {
 __device__ __forceinline__ void pub_flag(int* f, int v) {
     __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Wait until *f >= v.  The producer is resident and never waits on this
-// wave, so it gets there; the bound only guarantees that the wave ends.
-__device__ __forceinline__ void wait_flag(const int* f, int v) {
-    for (int it = 0; it < (1 << 22); ++it) {
+// Wait until *f >= v, polling at most max_polls times.  The producer is
+// resident and never waits on this wave, so it gets there; the bound only
+// guarantees that the wave ends.  A wave that gives up sets bit 0 of the
+// status word (the host reads it with tsqr_check_status) and goes on with
+// whatever rows are in memory: that factorisation's R and Q are then invalid,
+// but every wave still exits.  The fence after the wait keeps the compiler
+// from moving the loads of the published rows above the flag load (the rows
+// themselves are read with device-coherent loads, see pub_load).
+__device__ __forceinline__ void wait_flag(const int* f, int v, int max_polls, int* status) {
+    bool ok = false;
+    for (int it = 0; it < max_polls; ++it) {
         const int cur = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        if (cur >= v) return;
+        if (cur >= v) {
+            ok = true;
+            break;
+        }
         __builtin_amdgcn_s_sleep(2);
     }
+    if (!ok && (threadIdx.x & 63) == 0)
+        __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 // Level of the node that actually produces the R of tree position (l, idx):
 // positions with a single child pass their child's R up unchanged.
@@ -714,7 +735,7 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
     r_pub<T, NP>(sm, Rbuf + (int64_t)c * rs);
     pub_wait();
     if (lane == 0) pub_flag(prog + c, npl);
-    if (c == 0) return;
+    if (c % g.cpm == 0) return;  // a member's first chain performs no node
     const int lev = __builtin_ctz((unsigned)c) + 1;
     const int i0 = c - (1 << (lev - 1));
     const int la = producer_level(W, lev - 1, i0), lb = producer_level(W, lev - 1, c);
@@ -731,8 +752,8 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
         constexpr int p = decltype(pc)::value;
         constexpr int e0 = rpi<NCP>(16 * p, 16 * p);
         constexpr int e1 = (p + 1 < NP) ? rpi<NCP>(16 * (p + 1), 16 * (p + 1)) : RP;
-        wait_flag(prog + la * W + i0, p + 1);
-        if (!own_b) wait_flag(prog + lb * W + c, p + 1);
+        wait_flag(prog + la * W + i0, p + 1, ta.max_polls, ta.status);
+        if (!own_b) wait_flag(prog + lb * W + c, p + 1, ta.max_polls, ta.status);
         for (int e = e0 + lane; e < e1; e += 64) sm.R[e] = pub_load(Ra + e);
         if (!own_b) {
             typedef Mfma<T> M;
@@ -764,7 +785,7 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
         if constexpr (WQ) wstore<T, NP, NP>(x, Ynode + (int64_t)c * nn, n, 0, n, n);
     };
     wave_block<T, NP, NP, 2, WQ>(x, sm, n, Tnode + (int64_t)c * tri, tau_node + (int64_t)c * n, emit, pre, post);
-    if (lev == g.levels && ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
+    if (lev == g.levels && ta.Rout) r_out<T, NP>(sm, n, rout_of<T>(ta, i0 / g.cpm), ta.ldr, ta.zero_lower != 0);
 }
 
 template <typename T, int NP, int SG, bool PIPE = false, bool WQ = true>
@@ -805,11 +826,13 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         }
     }
     // ---- the tree
+    if (g.levels == 0) {  // every chain is a whole member
+        if (ta.Rout) r_out<T, NP>(sm, n, rout_of<T>(ta, c / g.cpm), ta.ldr, ta.zero_lower != 0);
+        return;
+    }
     if constexpr (PIPE) {
-        if (g.W > 1) {
-            wave_tree_pipe<T, NP, WQ>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
-            return;
-        }
+        wave_tree_pipe<T, NP, WQ>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
+        return;
     }
     const int64_t rs = rslot<NP>(n);
     int cur = c;
@@ -826,6 +849,8 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         if ((threadIdx.x & 63) == 0) old = atomicAdd(ta.cnt + (int64_t)(lev - 1) * g.W + i0, 1);
         old = __builtin_amdgcn_readfirstlane(old);
         if (old != nch - 1) return;
+        // the other children's published rows are read only after the count
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         // The node folds children 1..nch-1 into child 0 in order, whichever
         // child arrived last.  This wave's own R is taken from LDS, the others
         // from their published copies.
@@ -856,7 +881,7 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         }
         cur = i0;
     }
-    if (ta.Rout) r_out<T, NP>(sm, n, (T*)ta.Rout, ta.ldr, ta.zero_lower != 0);
+    if (ta.Rout) r_out<T, NP>(sm, n, rout_of<T>(ta, cur / g.cpm), ta.ldr, ta.zero_lower != 0);
 }
 
 }  // namespace tsqr

@@ -38,11 +38,23 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(block_rows=0, chains=0, arity=0, flags=0):
-    if not (block_rows or chains or arity or flags):
+def _opts(block_rows=0, chains=0, arity=0, flags=0, max_polls=0):
+    if not (block_rows or chains or arity or flags or max_polls):
         return None
-    o = _lib.opts(block_rows, chains, arity, flags)
+    o = _lib.opts(block_rows, chains, arity, flags, max_polls)
     return ctypes.byref(o)
+
+
+def check_status(stream=None) -> int:
+    """Wait for `stream` (default: the current stream) and return the
+    library's status for the current device: 0, or TSQR_ERR_TIMEOUT if a
+    bounded wait inside a factorisation gave up since the last check."""
+    lib = _lib.load()
+    st = torch.cuda.current_stream() if stream is None else stream
+    rc = lib.tsqr_check_status(ctypes.c_void_p(st.cuda_stream))
+    if rc not in (0, _lib.TSQR_ERR_TIMEOUT):
+        _lib.check("tsqr_check_status", rc)
+    return rc
 
 
 def plan_geometry(m: int, n: int, block_rows=0, chains=0, arity=0) -> dict:
@@ -74,6 +86,14 @@ class QTree:
         _lib.check("tsqr_qtree_info", _lib.load().tsqr_qtree_info(self._h, out))
         keys = ("m", "n", "block_rows", "chains", "arity", "levels", "blocks", "dtype", "kind", "panel")
         return dict(zip(keys, (int(v) for v in out)))
+
+    def wide_layout(self, k: int, panel: int = 0) -> bool:
+        """Whether applies with k columns take the wide kernels (panel: the
+        CAQR panel whose tree is applied; 0 for TSQR)."""
+        rc = _lib.load().tsqr_apply_layout(self._h, panel, k)
+        if rc < 0:
+            _lib.check("tsqr_apply_layout", rc)
+        return rc == 1
 
     def _check_b(self, B: torch.Tensor):
         if B.dtype != self.dtype or B.device != self.device:
@@ -115,12 +135,14 @@ class QTree:
 
 
 def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0,
-           levelwise: bool = False, want_q: bool = True):
+           levelwise: bool = False, want_q: bool = True, max_polls: int = 0):
     """TSQR of A (m x n, m >= n, n <= 64), IN PLACE: A is overwritten by the
     leaf reflectors.  Returns (R, QTree); diag(R) carries the Householder
     signs (see sign_normalize).  levelwise: reduce the tree node by node
     (TSQR_FLAG_TREE_LEVELWISE) instead of panel-pipelined; same result.
-    want_q=False: R only (no implicit Q is formed); returns (R, None)."""
+    want_q=False: R only (no implicit Q is formed); returns (R, None).
+    max_polls: bound of the pipelined tree's waits (tsqr_opts.max_polls;
+    0 = the library default), for tests of the give-up path."""
     lib = _lib.load()
     m, n = A.shape
     if R is None:
@@ -128,9 +150,45 @@ def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=
     h = ctypes.c_void_p()
     flags = _lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0
     rc = lib.tsqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(R), _ld(R),
-                         _opts(block_rows, chains, arity, flags), ctypes.byref(h) if want_q else None, _stream(A))
+                         _opts(block_rows, chains, arity, flags, max_polls), ctypes.byref(h) if want_q else None,
+                         _stream(A))
     _lib.check("tsqr_factor", rc)
     return R, (QTree(h, A, m, n) if want_q else None)
+
+
+def factor_batched(A: torch.Tensor, R: torch.Tensor | None = None, chains=0, arity=0, levelwise: bool = False,
+                   want_q: bool = True):
+    """TSQR of every matrix of a contiguous [batch, m, n] tensor (n <= 64),
+    IN PLACE: A is overwritten by the leaf reflectors.  Each member has its
+    own tree (chains = chains per member, a power of the arity; 0 = the
+    library's choice).  Returns (R [batch, n, n], QTree over the stacked
+    (batch*m) x n rows) or (R, None) without an implicit Q."""
+    lib = _lib.load()
+    if A.dim() != 3 or not A.is_contiguous():
+        raise ValueError("expected a contiguous [batch, m, n] tensor")
+    b, m, n = A.shape
+    if R is None:
+        R = torch.empty(b, n, n, dtype=A.dtype, device=A.device)
+    h = ctypes.c_void_p()
+    flags = _lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0
+    A2 = A.view(b * m, n)
+    rc = lib.tsqr_factor_batched(_dtype_code(A), b, m, n, _ptr(A2), n, _ptr(R), R.stride(1), R.stride(0),
+                                 _opts(0, chains, arity, flags), ctypes.byref(h) if want_q else None, _stream(A))
+    _lib.check("tsqr_factor_batched", rc)
+    return R, (QTree(h, A2, b * m, n) if want_q else None)
+
+
+def sign_normalize_batched(Q: torch.Tensor | None, R: torch.Tensor):
+    """Per member b: R_b <- D_b R_b, Q_b <- Q_b D_b (Q: [batch, m, n] or its
+    stacked 2-D view; R: [batch, n, n]), D_b = sign(diag R_b), in place."""
+    lib = _lib.load()
+    b, n = R.shape[0], R.shape[1]
+    m = (Q.numel() // (b * n)) if Q is not None else n
+    ldq = n
+    rc = lib.tsqr_sign_normalize_batched(_dtype_code(R), b, m, n, _ptr(Q) if Q is not None else None, ldq,
+                                         _ptr(R), R.stride(1), R.stride(0), _stream(R))
+    _lib.check("tsqr_sign_normalize_batched", rc)
+    return Q, R
 
 
 def lstsq(A: torch.Tensor, B: torch.Tensor, rnorm: bool = True, block_rows=0, chains=0, arity=0):
@@ -167,6 +225,18 @@ def cholqr(A: torch.Tensor, passes: int = 1, out_q: torch.Tensor | None = None):
     rc = lib.tsqr_cholqr(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(Q), _ld(Q), _ptr(R), _ld(R), int(passes),
                          _stream(A))
     _lib.check("tsqr_cholqr", rc)
+    return Q, R
+
+
+def mgs(A: torch.Tensor, out_q: torch.Tensor | None = None):
+    """Modified Gram-Schmidt of A (m x n, n <= 64), for comparison with TSQR:
+    returns (Q, R), diag(R) > 0.  A is not modified unless out_q is A."""
+    lib = _lib.load()
+    m, n = A.shape
+    Q = out_q if out_q is not None else torch.empty(m, n, dtype=A.dtype, device=A.device)
+    R = torch.empty(n, n, dtype=A.dtype, device=A.device)
+    rc = lib.tsqr_mgs(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(Q), _ld(Q), _ptr(R), _ld(R), _stream(A))
+    _lib.check("tsqr_mgs", rc)
     return Q, R
 
 
@@ -237,12 +307,14 @@ class TSQRFunction(torch.autograd.Function):
         batched = A.dim() == 3
         As = A.detach().contiguous()
         if batched:
-            Qs, Rs = [], []
-            for b in range(As.shape[0]):
-                Qb, Rb = qr(As[b], block_rows=block_rows, chains=chains, arity=arity)
-                Qs.append(Qb)
-                Rs.append(Rb)
-            Q, R = torch.stack(Qs), torch.stack(Rs)
+            # one factorisation of the whole batch (a forest of trees), then
+            # every member's explicit Q in one pass
+            W = As.clone()
+            R, qt = factor_batched(W, chains=chains, arity=arity)
+            Q = qt.form_q()
+            qt.close()
+            sign_normalize_batched(Q, R)
+            Q = Q.view(As.shape)
         else:
             Q, R = qr(As, block_rows=block_rows, chains=chains, arity=arity)
         ctx.save_for_backward(Q, R)

@@ -180,3 +180,36 @@ def test_header_is_plain_c():
     p = subprocess.run([gcc, "-fsyntax-only", "-x", "c", "-std=c99", "-Wall", "-Werror", hdr],
                        capture_output=True, text=True)
     assert p.returncode == 0, p.stderr
+
+
+def test_status_and_layout_calls_without_device_work():
+    lib = _lib.load()
+    assert lib.tsqr_status_string(_lib.TSQR_ERR_TIMEOUT).startswith(b"a bounded wait")
+    assert lib.tsqr_apply_layout(None, 0, 32) == -1
+
+
+def test_environment_does_not_change_the_tree(monkeypatch):
+    # tuning comes only from tsqr_opts: the library reads no environment variable
+    ref = plan_geometry(1 << 20, 64)
+    for name, val in (("TSQR_CHAINS", "7"), ("TSQR_ARITY", "4"), ("TSQR_BLOCK_ROWS", "32")):
+        monkeypatch.setenv(name, val)
+    assert plan_geometry(1 << 20, 64) == ref
+    assert ref["chains"] == 1024 and ref["arity"] == 2
+
+
+def test_opts_struct_matches_header():
+    src = open(os.path.join(ROOT, "include", "tsqr.h")).read()
+    body = re.search(r"typedef struct tsqr_opts \{(.*?)\} tsqr_opts;", src, flags=re.S).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == [f for f, _ in _lib.TsqrOpts._fields_]
+
+
+def test_mgs_argument_errors():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    f = vp(0x1000)  # never dereferenced: every call fails its checks first
+    assert lib.tsqr_mgs(7, 10, 4, f, 4, f, 4, f, 4, None) == -1
+    assert lib.tsqr_mgs(1, 3, 4, f, 4, f, 4, f, 4, None) == -2
+    assert lib.tsqr_mgs(1, 100, 65, f, 65, f, 65, f, 65, None) == _lib.TSQR_ERR_UNSUPPORTED
+    assert lib.tsqr_mgs(1, 100, 4, f, 4, f, 5, f, 4, None) == -7  # Q is A with another ld
+    assert lib.tsqr_mgs(1, 100, 4, f, 4, vp(0x2000), 4, None, 4, None) == -8

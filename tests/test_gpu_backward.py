@@ -96,17 +96,27 @@ def test_config5_fp64_262144x32():
     assert err <= 1e-11
 
 
-def test_config5_fp32_batch_sampled():
+def test_config5_fp32_batch_all_members():
+    """256 x 8192 x 32 FP32: the forward (one batched factorisation, every
+    member on its own tree, then one explicit-Q pass) and the gradient of
+    every member against the oracle on the rounded inputs."""
     import paper_0808_2664_amd as tq
-    _note("case: config5 fp32 batch 256x8192x32 (8 members checked)")
+    _note("case: config5 fp32 batch 256x8192x32 (all members)")
     A, dQ, dR = workloads.cfg5_batch()
     Ad = torch.from_numpy(A).cuda().requires_grad_(True)
     Q, R = tq.tsqr(Ad)
     loss = (Q * torch.from_numpy(dQ).cuda()).sum() + (R * torch.from_numpy(dR).cuda()).sum()
     (g,) = torch.autograd.grad(loss, Ad)
     g = g.double().cpu().numpy()
-    for b in [0, 1, 77, 128, 200, 253, 254, 255]:
+    Qg, Rg = Q.detach().double().cpu().numpy(), R.detach().double().cpu().numpy()
+    worst = [0.0, 0.0, 0.0]
+    for b in range(A.shape[0]):
         A64 = A[b].astype(np.float64)
         Qo, Ro = oracle.qr(A64)
         go = oracle.qr_adjoint(Qo, Ro, dQ[b].astype(np.float64), dR[b].astype(np.float64))
-        assert oracle.rel_err(g[b], go) <= 5e-4
+        worst[0] = max(worst[0], oracle.rel_err(Rg[b], Ro))
+        worst[1] = max(worst[1], oracle.rel_err(Qg[b], Qo))
+        worst[2] = max(worst[2], oracle.rel_err(g[b], go))
+    _note("  worst member errors: R %.2e, Q %.2e, gradient %.2e" % tuple(worst))
+    assert worst[0] <= 1e-5 and worst[1] <= 1e-5
+    assert worst[2] <= 5e-4

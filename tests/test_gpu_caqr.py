@@ -1,13 +1,13 @@
 """GPU parity of CAQR (TSQR panels + trailing update, Sec. 3) against the oracle.
 
-FP64 updates: normwise R error <= 1e-11 and backward error ||A - QR||/||A||
-<= 1e-13.  Orthogonality ||Q^T Q - I||_F of the n-column Q is gated at
-2.5e-16 * n: the Frobenius norm over n^2 entries of a product of n
-reflectors grows with n (the oracle's own Householder Q reaches 4.3e-14 at
-768 x 768 and 5.4e-14 at 1000 x 1000), so the fixed 1e-13 that suits 64
-columns is replaced by this n-proportional bound for the square cases.  FP32 updates on FP64 storage: the error is stated per result;
-the gates here are the FP32 scale (1e-4), far above what a correct run gives
-(~1e-6) and far below what a wrong reflector or sign gives (~1).
+FP64 updates: normwise R error <= 1e-11, backward error ||A - QR||/||A||
+<= 1e-13 and orthogonality ||Q^T Q - I||_F <= 1e-13 (the GPU and oracle
+values are printed; the oracle's own Q reaches 5.4e-14 at 1000 x 1000).  FP32 updates on FP64 storage (FP32 products subtracted into
+FP64 values): the error is stated per result; the gates here are the FP32
+scale (1e-4), far above what a correct run gives (~1e-6) and far below what
+a wrong reflector or sign gives (~1), and the error must be above the FP64
+level (the FP32 products really ran).  From 2048 rows the reference R is
+the oracle's blocked Householder QR (pinned against the unblocked loop).
 """
 import sys
 
@@ -61,7 +61,9 @@ def test_caqr_f64(m, n, panel):
     be = _backward_error(qt, A_keep, R, m, n)
     assert be <= 1e-13, be
     Q = qt.form_q().cpu().numpy()
-    assert oracle.orthogonality(Q) <= max(1e-13, 2.5e-16 * n)
+    orth, orth_o = oracle.orthogonality(Q), oracle.orthogonality(Qo)
+    _note("  orthogonality GPU %.2e, oracle %.2e" % (orth, orth_o))
+    assert orth <= 1e-13
     assert oracle.residual(A, Q, Rg) <= 1e-13
 
 
@@ -90,26 +92,66 @@ def test_caqr_f32_storage():
     assert _backward_error(qt, A_keep, R, 1200, 500) <= 1e-5
 
 
-def test_caqr_config3_full_size_sampled():
-    """16384 x 16384 Gaussian (seed 5), panel 64: sampled against the oracle.
-    R[:k,:k] is the R of A[:, :k]; R[:k, j] = Q_k^T a_j for sampled j; the
-    column norms of R equal those of A; backward error on the GPU."""
-    _note("case: caqr 16384^2 f64 (sampled)")
+def _oracle_r(A):
+    """Sign-normalised oracle R: the blocked Householder QR from 2048 rows."""
+    YR = oracle.geqrf_blocked(A, 64)[0] if A.shape[0] >= 2048 else oracle.geqrf(A)[0]
+    R = oracle.r_of(YR)
+    return R * oracle.signs(R)[:, None]
+
+
+def _r_err(R, Ro):
+    Rg = R.cpu().numpy()
+    return oracle.rel_err(Rg * oracle.signs(Rg)[:, None], Ro)
+
+
+@pytest.mark.parametrize("m,n,chains", [(2048, 1024, 32), (4096, 4096, 0)])
+def test_caqr_wide_kernels_both_updates(m, n, chains):
+    """Shapes whose trailing updates take the wide apply kernels (asserted
+    through tsqr_apply_layout): with the FP64 update and with FP32 products on
+    FP64 storage, the whole R against the oracle."""
+    A = workloads.gaussian(m, n, 400 + m + n)
+    Ro = _oracle_r(A)
+    kw = {"chains": chains} if chains else {}
+    for upd in (torch.float64, torch.float32):
+        _note("case: caqr %d x %d chains=%d update=%s" % (m, n, chains, upd))
+        R, qt, A_keep = _run(A, update=upd, **kw)
+        assert qt.wide_layout(n - 128, panel=0)
+        e = _r_err(R, Ro)
+        be = _backward_error(qt, A_keep, R, m, n)
+        _note("  R error %.2e, backward error %.2e" % (e, be))
+        if upd == torch.float64:
+            assert e <= 1e-11 and be <= 1e-13
+        else:
+            assert 1e-12 < e <= 1e-4 and be <= 1e-4
+        qt.close()
+
+
+@pytest.mark.timeout(1200)
+def test_caqr_config3_full_size_against_oracle():
+    """16384 x 16384 Gaussian (seed 5), panel 64, in the bench's launch
+    configuration (eight-block panel chains, wide kernels, look-ahead): the
+    whole R with the FP64 update and with FP32 products, against the oracle's
+    blocked Householder QR of the same matrix (about 1-3 minutes of host
+    cores), and the backward error of each on the GPU."""
     N = 16384
     A = workloads.cfg3(N)
-    R, qt, A_keep = _run(A)
-    Rg = R.cpu().numpy()
-    d = oracle.signs(Rg)
-    Rn = Rg * d[:, None]
-    k = 64
-    YRk, tauk = oracle.geqrf(A[:, :k])
-    Rk = oracle.r_of(YRk)
-    dk = oracle.signs(Rk)
-    assert oracle.rel_err(Rn[:k, :k], Rk * dk[:, None]) <= 1e-11
-    cols = np.array([100, 5000, 9999, 16383])
-    top = oracle.apply_qt(YRk, tauk, A[:, cols])[:k] * dk[:, None]
-    assert oracle.rel_err(Rn[:k, cols], top) <= 1e-11
-    np.testing.assert_allclose(np.linalg.norm(Rn, axis=0), np.linalg.norm(A, axis=0), rtol=1e-11)
-    be = _backward_error(qt, A_keep, R, N, N)
-    _note("  backward error %.2e" % be)
-    assert be <= 1e-13
+    errs = {}
+    Rs = {}
+    for upd in (torch.float64, torch.float32):
+        _note("case: caqr 16384^2 update=%s" % upd)
+        R, qt, A_keep = _run(A, update=upd)
+        assert qt.wide_layout(N - 128, panel=0) and qt.info()["panel"] == 64
+        be = _backward_error(qt, A_keep, R, N, N)
+        Rs[upd] = R.cpu().numpy()
+        errs[upd] = be
+        qt.close()
+        del R, qt, A_keep
+        torch.cuda.empty_cache()
+    _note("  oracle (blocked, %d threads)" % oracle.set_threads(0))
+    Ro = _oracle_r(A)
+    e64 = oracle.rel_err(Rs[torch.float64] * oracle.signs(Rs[torch.float64])[:, None], Ro)
+    e32 = oracle.rel_err(Rs[torch.float32] * oracle.signs(Rs[torch.float32])[:, None], Ro)
+    _note("  R error vs oracle: FP64 update %.2e, FP32 update %.2e; backward error %.2e / %.2e"
+          % (e64, e32, errs[torch.float64], errs[torch.float32]))
+    assert e64 <= 1e-11 and errs[torch.float64] <= 1e-13
+    assert 1e-12 < e32 <= 1e-4 and errs[torch.float32] <= 1e-4

@@ -267,17 +267,24 @@ def test_ill_conditioned_1e8():
     _check(A, B, g, o, rtol_r=1e-11, rtol_q=tol_q)
 
 
-def test_config2_full_size_sampled():
-    """2^20 x 64, cond 1e8: the configuration the bench times.  Sampled
-    against the oracle (plus the full R): R's leading 16 x 16 block equals the R of A[:, :16];
-    R's first 16 rows equal Q_16^T A; every column norm of R equals that of A;
-    residual and orthogonality of the full factorisation."""
+def test_config2_full_size_against_oracle():
+    """2^20 x 64, cond 1e8, B 2^20 x 32: the configuration the bench times, in
+    the bench's launch configuration (1024 chains of 16 blocks, pipelined
+    tree, wide apply kernels).  The whole R, the whole thin Q and the whole
+    thin Q^T B against the oracle's Householder QR (the oracle's form_q and
+    apply_qt on its own reflectors); R is also pinned by its leading block
+    (the R of A[:, :16]) and its column norms; residual and orthogonality."""
     _note("case: config2 full size")
     A, B = workloads.cfg2()
-    Ro_full = oracle.r_of(oracle.geqrf(A)[0])
+    YRo, tauo = oracle.geqrf(A)
+    Ro_full = oracle.r_of(YRo)
+    do = oracle.signs(Ro_full)
     import paper_0808_2664_amd as tq
     Ad = _dev(A)
     R, qt = tq.factor(Ad)
+    info = qt.info()
+    assert info["chains"] == 1024 and info["blocks"] == 16384
+    assert qt.wide_layout(32) and qt.wide_layout(64)
     Q = qt.form_q()
     Bd = _dev(B)
     qt.apply_qt(Bd)
@@ -290,17 +297,62 @@ def test_config2_full_size_sampled():
     Rk = oracle.r_of(YRk)
     dk = oracle.signs(Rk)
     assert oracle.rel_err(Rn[:k, :k], Rk * dk[:, None]) <= 1e-11
-    top = oracle.apply_qt(YRk, tauk, A[:, k:])[:k] * dk[:, None]
-    assert oracle.rel_err(Rn[:k, k:], top) <= 1e-11
     np.testing.assert_allclose(np.linalg.norm(Rn, axis=0), np.linalg.norm(A, axis=0), rtol=1e-12)
-    # the whole R against the oracle (about 8 s of CPU)
-    assert oracle.rel_err(Rn, Ro_full * oracle.signs(Ro_full)[:, None]) <= 1e-11
+    assert oracle.rel_err(Rn, Ro_full * do[:, None]) <= 1e-11
+    # thin Q and thin Q^T B against the oracle: at cond 1e8 two correct QRs
+    # differ by about cond * u in these, so the gate is 100 cond u
+    gate = 100 * 1e8 * U64
+    Qo = oracle.form_q(YRo, tauo) * do[None, :]
+    Qn = Q.cpu().numpy() * d[None, :]
+    eq = oracle.rel_err(Qn, Qo)
+    thin_o = oracle.apply_qt(YRo, tauo, B)[:64] * do[:, None]
+    thin = Bd[:64].cpu().numpy() * d[:, None]
+    eb = oracle.rel_err(thin, thin_o)
+    _note("  Q error %.2e, thin Q^T B error %.2e (gate %.1e)" % (eq, eb, gate))
+    assert eq <= gate and eb <= gate
+    # the trailing rows of Q^T B depend on the tree; their column norms do not
+    tail_o = np.linalg.norm(oracle.apply_qt(YRo, tauo, B)[64:], axis=0)
+    tail = torch.linalg.norm(Bd[64:], dim=0).cpu().numpy()
+    np.testing.assert_allclose(tail, tail_o, rtol=1e-11)
     Qd = Q * _dev(d)[None, :]
     Rd = _dev(Rn)
     res = (torch.linalg.norm(_dev(A) - Qd @ Rd) / torch.linalg.norm(_dev(A))).item()
     orth = torch.linalg.norm(_gram_pairwise(Qd) - torch.eye(64, dtype=torch.float64, device="cuda")).item()
     assert res <= 1e-13 and orth <= 1e-13
-    # thin Q^T B: rows 0..n-1 equal Q^T B with the explicit Q
-    thin = (Bd[:64] * _dev(d)[:, None])
-    ref = Qd.T @ _dev(B)
-    assert (torch.linalg.norm(thin - ref) / torch.linalg.norm(ref)).item() <= 1e-12
+    qt.close()
+
+
+@pytest.mark.parametrize("k", [32, 64])
+def test_f32_wide_apply_against_oracle(k):
+    """FP32 storage and compute with the wide apply kernels (2^16 x 64, 1024
+    chains): Q^T B, Q B and the explicit Q against the oracle run in FP64 on
+    the rounded inputs."""
+    _note("case: f32 wide apply k=%d" % k)
+    m, n = 1 << 16, 64
+    A = workloads.gaussian(m, n, 910).astype(np.float32)
+    B = workloads.gaussian(m, k, 911).astype(np.float32)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    import paper_0808_2664_amd as tq
+    Ad = _dev(A, torch.float32)
+    R, qt = tq.factor(Ad)
+    assert qt.wide_layout(k)
+    Q = qt.form_q()
+    Bd = _dev(B, torch.float32)
+    qt.apply_qt(Bd)
+    thin = Bd[:n].double().cpu().numpy()
+    tail = torch.linalg.norm(Bd[n:].double(), dim=0).cpu().numpy()
+    qt.apply_q(Bd)
+    back = Bd.double().cpu().numpy()
+    torch.cuda.synchronize()
+    YRo, tauo = oracle.geqrf(A64)
+    Ro = oracle.r_of(YRo)
+    do = oracle.signs(Ro)
+    Rg = R.double().cpu().numpy()
+    d = oracle.signs(Rg)
+    assert oracle.rel_err(Rg * d[:, None], Ro * do[:, None]) <= 1e-5
+    assert oracle.rel_err(Q.double().cpu().numpy() * d[None, :], oracle.form_q(YRo, tauo) * do[None, :]) <= 1e-5
+    full_o = oracle.apply_qt(YRo, tauo, B64)
+    assert oracle.rel_err(thin * d[:, None], full_o[:n] * do[:, None]) <= 1e-5
+    np.testing.assert_allclose(tail, np.linalg.norm(full_o[n:], axis=0), rtol=1e-5)
+    assert oracle.rel_err(back, B64) <= 1e-5  # Q (Q^T B) = B
+    qt.close()
