@@ -33,11 +33,14 @@
  *    TSQR_ERR_UNSUPPORTED  n > 64 for TSQR, or an unsupported option
  *    TSQR_ERR_TIMEOUT   (tsqr_check_status only) a bounded wait inside a
  *                       factorisation gave up; its results are invalid
+ *    TSQR_ERR_SCRATCH   (tsqr_factor_noalloc only) the problem needs more
+ *                       scratch memory than the fixed buffer holds
  * NaN/Inf inputs are not detected; they propagate to the outputs.
  */
 #ifndef TSQR_H
 #define TSQR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -53,6 +56,7 @@ extern "C" {
 #define TSQR_ERR_PLAN 3
 #define TSQR_ERR_UNSUPPORTED 4
 #define TSQR_ERR_TIMEOUT 5
+#define TSQR_ERR_SCRATCH 6
 
 #define TSQR_MAX_N 64
 
@@ -110,6 +114,27 @@ typedef struct tsqr_opts {
  *   8 opts, 9 q_out. */
 int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
                 const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
+/* R-only TSQR that allocates nothing, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, kernels and results (bit for
+ * bit) as tsqr_factor with q_out = NULL: A is overwritten with the leaf
+ * reflectors, R (device n x n, ldr >= n, required) receives R with zeros
+ * below the diagonal.  The factor's scratch memory (the chains' published R
+ * factors and the tree's counters) is a fixed device array of
+ * tsqr_factor_noalloc_scratch_bytes() bytes (40 MiB) that each device the
+ * library runs on holds until the process ends; the call makes no device
+ * allocation and no free.  Problems whose scratch exceeds it (more than 1024
+ * chains of 64 columns in FP64 with the default tree; the default geometry
+ * of every m fits) return TSQR_ERR_SCRATCH before any launch.  Every call on
+ * a device shares that device's array: calls that overlap on one device (two
+ * streams or two host threads) race and must be serialised by the caller.
+ *   Argument indices for errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 R, 7 ldr,
+ *   8 opts. */
+int tsqr_factor_noalloc(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
+                        const tsqr_opts* opts, void* stream);
+/* Size in bytes of tsqr_factor_noalloc's fixed scratch array (per device). */
+size_t tsqr_factor_noalloc_scratch_bytes(void);
 
 /* Layout the apply kernels take for k columns of B on this implicit Q
  * (panel `panel` of a CAQR handle, whose trailing updates are Q^T products

@@ -20,6 +20,7 @@ TSQR_ERR_NOMEM = 2
 TSQR_ERR_PLAN = 3
 TSQR_ERR_UNSUPPORTED = 4
 TSQR_ERR_TIMEOUT = 5
+TSQR_ERR_SCRATCH = 6
 TSQR_MAX_N = 64
 TSQR_FLAG_TREE_LEVELWISE = 1
 
@@ -80,6 +81,7 @@ def load():
         "tsqr_factor_batched": [i32, i64, i64, i64, vp, i64, vp, i64, i64, popts, ctypes.POINTER(vp), vp],
         "tsqr_qtree_members": [vp, p64],
         "tsqr_sign_normalize_batched": [i32, i64, i64, i64, vp, i64, vp, i64, i64, vp],
+        "tsqr_factor_noalloc": [i32, i64, i64, vp, i64, vp, i64, popts, vp],
         "tsqr_set_phase_events": [i32, vp, vp],
         "caqr_factor": [i32, i64, i64, vp, i64, i64, i32, popts, ctypes.POINTER(vp), vp],
         "tsqr_copy_r": [i32, i64, vp, i64, vp, i64, vp],
@@ -94,6 +96,8 @@ def load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.tsqr_factor_noalloc_scratch_bytes.argtypes = []
+    lib.tsqr_factor_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.tsqr_status_string.argtypes = [ctypes.c_int]
     lib.tsqr_status_string.restype = ctypes.c_char_p
     _lib = lib

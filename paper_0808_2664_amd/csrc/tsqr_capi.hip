@@ -666,6 +666,7 @@ const char* tsqr_status_string(int status) {
         case TSQR_ERR_PLAN: return "handle or shape mismatch";
         case TSQR_ERR_UNSUPPORTED: return "unsupported size or option";
         case TSQR_ERR_TIMEOUT: return "a bounded wait inside a factorisation gave up; its results are invalid";
+        case TSQR_ERR_SCRATCH: return "the problem needs more scratch memory than the fixed buffer holds";
         default: return status < 0 ? "invalid argument" : "unknown status";
     }
 }

@@ -213,3 +213,17 @@ def test_mgs_argument_errors():
     assert lib.tsqr_mgs(1, 100, 65, f, 65, f, 65, f, 65, None) == _lib.TSQR_ERR_UNSUPPORTED
     assert lib.tsqr_mgs(1, 100, 4, f, 4, f, 5, f, 4, None) == -7  # Q is A with another ld
     assert lib.tsqr_mgs(1, 100, 4, f, 4, vp(0x2000), 4, None, 4, None) == -8
+
+
+def test_noalloc_argument_errors_without_launch():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    f = vp(0x1000)  # never dereferenced: every call fails its checks first
+    g = lib.tsqr_factor_noalloc
+    assert g(7, 100, 4, f, 4, f, 4, None, None) == -1
+    assert g(1, 3, 4, f, 4, f, 4, None, None) == -2
+    assert g(1, 100, 4, None, 4, f, 4, None, None) == -4
+    assert g(1, 100, 4, f, 4, None, 4, None, None) == -6   # R is required
+    big = _lib.opts(chains=4096)  # 4096 chain R slots of 64 x 64 FP64 exceed the fixed scratch
+    assert g(1, 1 << 20, 64, f, 64, f, 64, ctypes.byref(big), None) == _lib.TSQR_ERR_SCRATCH
+    assert lib.tsqr_factor_noalloc_scratch_bytes() == 40 << 20
