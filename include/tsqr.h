@@ -73,7 +73,13 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                min(number of blocks, 1024).  chains = number of blocks
  *                gives the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
  *   arity      : fan-in of the tree over the chain R factors (default 2).
- *   flags      : 0 or TSQR_FLAG_TREE_LEVELWISE.  By default a binary tree
+ *   flags      : 0, TSQR_FLAG_TREE_LEVELWISE, TSQR_FLAG_ONE_WAVE or both.
+ *                TSQR_FLAG_ONE_WAVE: every chain on the one-wave engine
+ *                (chains and tree in one launch) also where the default is
+ *                the two-wave chain engine (FP64, more than 32 columns:
+ *                two waves split a chain's columns, then the tree in a
+ *                second launch); both give the same bits.
+ *                TSQR_FLAG_TREE_LEVELWISE: By default a binary tree
  *                whose chains all fit on the device at once is reduced
  *                panel by panel (a node starts on its first 16 columns as
  *                soon as its children have finished theirs); with this flag,
@@ -92,6 +98,8 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  * The library reads no environment variable: these fields are the only
  * tuning inputs. */
 #define TSQR_FLAG_TREE_LEVELWISE 1
+#define TSQR_FLAG_ONE_WAVE 2
+#define TSQR_FLAGS_ALL (TSQR_FLAG_TREE_LEVELWISE | TSQR_FLAG_ONE_WAVE)
 typedef struct tsqr_opts {
     int32_t block_rows;
     int32_t chains;

@@ -23,6 +23,7 @@ TSQR_ERR_TIMEOUT = 5
 TSQR_ERR_SCRATCH = 6
 TSQR_MAX_N = 64
 TSQR_FLAG_TREE_LEVELWISE = 1
+TSQR_FLAG_ONE_WAVE = 2
 
 
 class TsqrOpts(ctypes.Structure):

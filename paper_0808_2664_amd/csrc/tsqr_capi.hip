@@ -86,7 +86,7 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     int chains = (o && o->chains) ? o->chains : 0;
     int arity = (o && o->arity) ? o->arity : 2;
     const int flags = o ? o->flags : 0;
-    if (flags & ~TSQR_FLAG_TREE_LEVELWISE) return TSQR_ERR_UNSUPPORTED;
+    if (flags & ~TSQR_FLAGS_ALL) return TSQR_ERR_UNSUPPORTED;
     if (!wave_shape_ok(NC, h)) return TSQR_ERR_UNSUPPORTED;
     if (arity < 2 || chains < 0) return TSQR_ERR_UNSUPPORTED;
     const int64_t blocks_total = (m + h - 1) / h;
@@ -114,7 +114,7 @@ int make_geom(int64_t m, int64_t n, const tsqr_opts* o, Geom* g) {
     const int64_t last = m - (W - 1) * S;
     g->nblocks = (W - 1) * (S / h) + (last + h - 1) / h;
     g->NC = padded_nc(n);
-    g->flags = (flags & TSQR_FLAG_TREE_LEVELWISE) ? TREE_LEVELWISE : 0;
+    g->flags = ((flags & TSQR_FLAG_TREE_LEVELWISE) ? TREE_LEVELWISE : 0) | ((flags & TSQR_FLAG_ONE_WAVE) ? ONE_WAVE : 0);
     g->mb = m;
     g->cpm = (int)W;
     g->bpm = g->nblocks;
@@ -272,7 +272,7 @@ int tsqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, 
     if (!A) return -4;
     if (lda < n) return -5;
     if (R && ldr < n) return -7;
-    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -8;
     if (!R && !q_out) return -9;
     tsqr_qtree_s* q = nullptr;
     int rc = factor_impl(dtype, m, n, A, lda, R, ldr, false, opts, &q, (hipStream_t)stream, q_out != nullptr);
@@ -293,7 +293,7 @@ int tsqr_factor_batched(int dtype, int64_t batch, int64_t m, int64_t n, void* A,
     if (lda < n) return -6;
     if (R && ldr < n) return -8;
     if (R && batch > 1 && strideR < n * ldr) return -9;
-    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -10;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -10;
     if (!R && !q_out) return -11;
     Geom g;
     // about one chain per SIMD (two for FP32, whose factor kernel fits two waves)
@@ -349,7 +349,7 @@ int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k,
     if (k < 0) return -6;
     if (k > 0 && !B) return -7;
     if (k > 0 && ldb < k) return -8;
-    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -10;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -10;
     if (k > ((int64_t)1 << 36)) return TSQR_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = dtype == TSQR_F64;
@@ -445,7 +445,7 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     if (panel < 1 || panel > TSQR_MAX_N) return -6;
     if (!check_dtype(update_dtype)) return -7;
     if (update_dtype == TSQR_F64 && dtype == TSQR_F32) return -7;
-    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -8;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = dtype == TSQR_F64;
     const bool cf64 = update_dtype == TSQR_F64;

@@ -36,6 +36,9 @@ struct Geom {
 // Geom::flags: reduce the tree node by node as children complete, never with
 // the panel-pipelined tree (the tsqr_opts flag of the same meaning).
 constexpr int TREE_LEVELWISE = 1;
+// Geom::flags: reduce every chain with the one-wave engine, also where the
+// two-wave chain engine applies (FP64, more than 32 columns).
+constexpr int ONE_WAVE = 2;
 
 // Chain c is chain c % cpm of member c / cpm; a member's last chain takes
 // the member's remaining rows.

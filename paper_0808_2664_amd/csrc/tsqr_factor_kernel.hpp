@@ -4,6 +4,7 @@
 // instantiation), so the fully unrolled column sweeps compile in parallel.
 #pragma once
 #include "tsqr_wave.hpp"
+#include "tsqr_wave2.hpp"
 
 namespace tsqr {
 
@@ -17,17 +18,20 @@ struct WaveOcc {
 
 // PIPE: the panel-pipelined binary tree; launched cooperatively, so that
 // every wave is resident and a node's wave may wait for its children.
-template <typename T, int NP, int SG, bool PIPE, bool WQ>
+// CHAIN = false: the chains were reduced by the two-wave chain kernel, whose
+// R factors are in Rbuf; this launch runs the tree only.
+template <typename T, int NP, int SG, bool PIPE, bool WQ, bool CHAIN>
 __global__ __launch_bounds__(64, WaveOcc<T>::value) void k_wave_tsqr(Geom g, T* __restrict__ A, int64_t lda, T* __restrict__ tau_blk,
                                                      T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                                      T* __restrict__ Ynode, T* __restrict__ Tnode,
                                                      T* __restrict__ tau_node, TreeArgs ta) {
     __shared__ WSmem<T, NP> sm;
-    wave_tsqr<T, NP, SG, PIPE, WQ>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
+    wave_tsqr<T, NP, SG, PIPE, WQ, CHAIN>(sm, g, (int)blockIdx.x, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node,
+                                          ta);
 }
 
-// Workgroups of k_wave_tsqr<T, NP, SG, true, WQ> the device keeps resident at once.
-template <typename T, int NP, int SG, bool WQ>
+// Workgroups of k_wave_tsqr<T, NP, SG, true, WQ, CHAIN> the device keeps resident at once.
+template <typename T, int NP, int SG, bool WQ, bool CHAIN>
 static int64_t pipe_capacity() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -36,7 +40,8 @@ static int64_t pipe_capacity() {
     if (dev < 0 || dev >= 64) return 0;
     if (!done[dev]) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true, WQ>, 64, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_tsqr<T, NP, SG, true, WQ, CHAIN>, 64, 0) !=
+                hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
             per_cu = 0;
@@ -47,22 +52,41 @@ static int64_t pipe_capacity() {
     return cap[dev];
 }
 
-template <typename T, int NP, int SG, bool WQ>
-hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
+// The tree (and, with CHAIN, the chains) in one launch.
+template <typename T, int NP, int SG, bool WQ, bool CHAIN>
+static hipError_t launch_tree(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
     T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
     T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
-    const bool pipe = g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ>();
+    const bool pipe =
+        g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ, CHAIN>();
     if (pipe) {
         Geom gg = g;
         TreeArgs tt = ta;
         void* args[] = {&gg, &A, &lda, &tau_blk, &T_blk, &Rbuf, &Ynode, &Tnode, &tau_node, &tt};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true, WQ>, dim3(g.W), dim3(64),
-                                                  args, 0, st);
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true, WQ, CHAIN>, dim3(g.W),
+                                                  dim3(64), args, 0, st);
         if (e == hipSuccess) return hipSuccess;
         (void)hipGetLastError();  // not co-resident after all: reduce level by level
     }
-    k_wave_tsqr<T, NP, SG, false, WQ><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode, tau_node, ta);
+    k_wave_tsqr<T, NP, SG, false, WQ, CHAIN><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode,
+                                                                 tau_node, ta);
     return hipGetLastError();
+}
+
+// FP64 with more than 32 columns: the chains on the two-wave engine
+// (tsqr_wave2.hpp), then the tree in a second launch; otherwise (and with
+// Geom::flags ONE_WAVE) chains and tree in one launch of the one-wave engine.
+template <typename T, int NP, int SG, bool WQ>
+hipError_t launch_wave(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
+    if constexpr (NP == 4 && sizeof(T) == 8) {
+        if (!(g.flags & ONE_WAVE)) {
+            k_chain2<T, WQ><<<g.W, 128, 0, st>>>(g, A, lda, (T*)wk.tau_blk, (T*)wk.T_blk, (T*)wk.Rbuf);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_tree<T, NP, SG, WQ, false>(g, A, lda, wk, ta, st);
+        }
+    }
+    return launch_tree<T, NP, SG, WQ, true>(g, A, lda, wk, ta, st);
 }
 
 }  // namespace tsqr

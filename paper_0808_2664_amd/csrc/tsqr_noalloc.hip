@@ -73,7 +73,7 @@ int tsqr_factor_noalloc(int dtype, int64_t m, int64_t n, void* A, int64_t lda, v
     if (lda < n) return -5;
     if (!R) return -6;
     if (ldr < n) return -7;
-    if (opts && (opts->flags & ~TSQR_FLAG_TREE_LEVELWISE)) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -8;
     tsqr::Geom g;
     int rc = tsqr::make_geom(m, n, opts, &g);
     if (rc != 0) return rc == -1 ? -2 : rc;

@@ -197,32 +197,49 @@ __device__ __forceinline__ int64_t tpi(int i, int j) { return (int64_t)j * (j + 
 
 // ---- the block factorisation -----------------------------------------------------
 //
-// After the panels, emit() is called while the tile still holds the final
-// reflectors (it stores them); the off-diagonal blocks of T follow from
-// registers, so the tile's registers are free again by then.
+// Hooks.  pre(p) runs before panel p and post(p) once panel p's rows of R
+// are final (its sweep and its update of the trailing columns are done).
+// done(p) runs as soon as column tile p holds its final values (reflector
+// tails, and R above them in a chain's first block), so its store overlaps
+// the rest of the block instead of all tiles leaving at the end; free(p)
+// once tile p's registers are no longer read (the next block may be loaded
+// into them): right after panel p when no Q is kept, after the last panel's
+// Gram products when it is.  emit() runs after the panels (a tree node
+// stores its reflectors there).  Every hook is called for every panel,
+// also for panels beyond n (zero columns), in panel order.
 struct NoHook {
     template <typename P>
     __device__ void operator()(P) const {}
 };
 
-// pre(p) runs before panel p and post(p) once panel p's rows of R are final
-// (its sweep and its update of the trailing columns are done).  WQ = false:
-// only R and the reflectors are wanted (no Q is kept), so tau and T are
-// neither stored nor, above the panels' diagonal blocks, formed.
+// WQ = false: only R and the reflectors are wanted (no Q is kept), so tau
+// and T are neither stored nor, above the panels' diagonal blocks, formed.
 template <typename T, int NP, int SG, int MODE, bool WQ = true, typename Emit, typename Pre = NoHook,
-          typename Post = NoHook>
+          typename Post = NoHook, typename Done = NoHook, typename Free = NoHook>
 __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, const int n_, T* __restrict__ Tout,
                                            T* __restrict__ tauout, Emit&& emit, Pre&& pre = Pre{},
-                                           Post&& post = Post{}) {
+                                           Post&& post = Post{}, Done&& done = Done{}, Free&& free_ = Free{}) {
     typedef Mfma<T> M;
     typedef typename M::acc acc_t;
     constexpr int NCP = 16 * NP;
+    // Gram blocks P_ac = V_a^T V_c (a < c) for the off-diagonal blocks of T,
+    // each formed as soon as panel c is done (MFMA(V_c, V_a) gives P_ac in
+    // the A-operand layout); rows where V_c or V_a vanishes are skipped:
+    // above panel c's heads in the first block, below panel a's rows in a
+    // tree node.
+    acc_t P[NP][NP];
 
     sfor<0, NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int c0 = 16 * p;
         const int n = opaque_s(n_);
-        if (c0 >= n) return;
+        if (c0 >= n) {
+            if constexpr (WQ && NP > 1 && p > 0)
+                sfor<0, p>([&](auto ac_) { P[decltype(ac_)::value][p] = acc_t{0, 0, 0, 0}; });
+            done(pc);
+            if constexpr (!WQ) free_(pc);
+            return;
+        }
         pre(pc);
         const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
         // live row groups of this panel
@@ -256,7 +273,9 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             }
             // column j, broadcast to the lanes of the other columns (tail rows only)
             T xj[SG][4];
-            T a0 = T(0), a1 = T(0);
+            // four running sums (one per register of a row group), so the
+            // dependent chain is one FMA per row group
+            T acc4[4] = {T(0), T(0), T(0), T(0)};
             sfor<S0, S1>([&](auto sc) {
                 constexpr int s = decltype(sc)::value;
 #pragma unroll
@@ -264,11 +283,10 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                     T v = bcast16<jj>(x[s][i][p]);
                     if constexpr (MODE == 0 && s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
                     xj[s][i] = v;
-                    if (i & 1) a1 = fma(v, x[s][i][p], a1);
-                    else a0 = fma(v, x[s][i][p], a0);
+                    acc4[i] = fma(v, x[s][i][p], acc4[i]);
                 }
             });
-            const T g = sum4(a0 + a1);
+            const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
             const T sigma2 = bcast16<jj>(g);
             T beta, tau, scale;
             hh_scalars(alpha, sigma2, beta, tau, scale);
@@ -302,12 +320,14 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             // in-panel Gram P[c][j] = v_c^T v_j (lanes c < j) and column j of the
             // panel's T (row l16 per lane group, kept in sm.td[p]):
             // T[a][j] = -tau_j sum_{k<j} T[a][k] P[k][j], T[j][j] = tau_j
+            // (two running sums over k, so the sum is not one dependent chain)
             const T pw = sc_lane * w;
-            T t = T(0);
+            T tk[2] = {T(0), T(0)};
             sfor<0, jj>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                t = fma(sm.td[p][l16][k], bcast16<k>(pw), t);
+                tk[k & 1] = fma(sm.td[p][l16][k], bcast16<k>(pw), tk[k & 1]);
             });
+            const T t = tk[0] + tk[1];
             sm.td[p][l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
         });
 
@@ -323,6 +343,28 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             }
         });
         if (WQ && l4 == 0 && c < n) tauout[c] = tau_lane;
+        done(pc);
+        if constexpr (WQ && NP > 1 && p > 0) {
+            sfor<0, p>([&](auto ac_) {
+                constexpr int a = decltype(ac_)::value;
+                P[a][p] = acc_t{0, 0, 0, 0};
+            });
+            sfor<0, SG>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    sfor<0, p>([&](auto ac_) {
+                        constexpr int a = decltype(ac_)::value;
+                        constexpr bool live = (MODE == 0) ? (s >= p) : ((MODE == 2) ? (s <= a) : true);
+                        if constexpr (live) {
+                            T vc = x[s][i][p];
+                            if constexpr (MODE == 0 && s == p) vc = vmask(vc, M::orow(l4, i), l16);
+                            P[a][p] = M::mma(vc, x[s][i][a], P[a][p]);
+                        }
+                    });
+                }
+            });
+        }
 
         // diagonal T block in the MFMA D layout; to global
         wave_sync();
@@ -423,61 +465,32 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                 });
             }
         }
+        if constexpr (MODE == 0 && p < SG) {
+            // rows of row group p of the block's R are final: into the on-chip R
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * p + M::orow(l4, i);
+                sfor<p, NP>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    const int cc = 16 * q + l16;
+                    if (r < n && cc >= r && cc < n) sm.R[rpi<NCP>(r, cc)] = x[p][i][q];
+                });
+            }
+        }
         post(pc);
+        if constexpr (!WQ) free_(pc);
     });
 
     const int n = opaque_s(n_);
     const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
-    if constexpr (MODE == 0) {
-        // R of the block: the upper triangle of its first n rows
-        sfor<0, (SG < NP ? SG : NP)>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 16 * s + M::orow(l4, i);
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const int cc = 16 * q + l16;
-                    if (r < n && cc >= r && cc < n) sm.R[rpi<NCP>(r, cc)] = x[s][i][q];
-                }
-            }
-        });
-    }
+    (void)l4;
 
     if constexpr (NP == 1 || !WQ) {
+        if constexpr (WQ) free_(ic_t<0>{});
         emit();
     } else {
         // ------------------------------------------------------ T blocks above the diagonal
-        // Gram blocks P_ac = V_a^T V_c (a < c), from MFMA(V_c, V_a): the result
-        // is P_ac in the A-operand layout.  Rows where V_c or V_a vanishes are
-        // skipped: above panel c's heads in the first block, below panel a's
-        // rows in a tree node.
-        acc_t P[NP][NP];
-        sfor<1, NP>([&](auto cc_) {
-            constexpr int cq = decltype(cc_)::value;
-            sfor<0, cq>([&](auto ac_) {
-                constexpr int a = decltype(ac_)::value;
-                P[a][cq] = acc_t{0, 0, 0, 0};
-            });
-        });
-        sfor<0, SG>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                sfor<1, NP>([&](auto cc_) {
-                    constexpr int cq = decltype(cc_)::value;
-                    sfor<0, cq>([&](auto ac_) {
-                        constexpr int a = decltype(ac_)::value;
-                        constexpr bool live = (MODE == 0) ? (s >= cq) : ((MODE == 2) ? (s <= a) : true);
-                        if constexpr (live) {
-                            T vc = x[s][i][cq];
-                            if constexpr (MODE == 0 && s == cq) vc = vmask(vc, M::orow(l4, i), l16);
-                            P[a][cq] = M::mma(vc, x[s][i][a], P[a][cq]);
-                        }
-                    });
-                });
-            }
-        });
+        sfor<0, NP>([&](auto pc) { free_(pc); });
         emit();
         // diagonal blocks from LDS: D layout (tD) and A-operand layout (tA)
         // (entries beyond n and below the diagonal are zero in td)
@@ -551,6 +564,54 @@ __device__ __forceinline__ void wload(T (&x)[SG][4][NP], const T* __restrict__ A
                 const int cc = 16 * q + l16;
                 x[s][i][q] = (r < rows && cc < n) ? A[(r0 + r) * lda + cc] : T(0);
             }
+        }
+}
+
+// One column tile q (columns 16q..16q+15) of a block.
+template <typename T, int NP, int SG, int Q>
+__device__ __forceinline__ void wload_tile(T (&x)[SG][4][NP], const T* __restrict__ A, int64_t lda, int64_t r0,
+                                           int rows, int n) {
+    typedef Mfma<T> M;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    if (rows == 16 * SG && n == 16 * NP) {
+        const T* __restrict__ pb = A + (r0 + M::orow(l4, 0)) * lda + 16 * Q + l16;
+#pragma unroll
+        for (int s = 0; s < SG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[s][i][Q] = pb[(int64_t)(16 * s + M::orow(0, i) - M::orow(0, 0)) * lda];
+        return;
+    }
+    const int cc = 16 * Q + l16;
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * s + M::orow(l4, i);
+            x[s][i][Q] = (r < rows && cc < n) ? A[(r0 + r) * lda + cc] : T(0);
+        }
+}
+
+template <typename T, int NP, int SG, int Q>
+__device__ __forceinline__ void wstore_tile(const T (&x)[SG][4][NP], T* __restrict__ A, int64_t lda, int64_t r0,
+                                            int rows, int n) {
+    typedef Mfma<T> M;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    if (rows == 16 * SG && n == 16 * NP) {
+        T* __restrict__ pb = A + (r0 + M::orow(l4, 0)) * lda + 16 * Q + l16;
+#pragma unroll
+        for (int s = 0; s < SG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pb[(int64_t)(16 * s + M::orow(0, i) - M::orow(0, 0)) * lda] = x[s][i][Q];
+        return;
+    }
+    const int cc = 16 * Q + l16;
+    if (cc >= n) return;
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * s + M::orow(l4, i);
+            if (r < rows) A[(r0 + r) * lda + cc] = x[s][i][Q];
         }
 }
 
@@ -754,7 +815,19 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
         constexpr int e1 = (p + 1 < NP) ? rpi<NCP>(16 * (p + 1), 16 * (p + 1)) : RP;
         wait_flag(prog + la * W + i0, p + 1, ta.max_polls, ta.status);
         if (!own_b) wait_flag(prog + lb * W + c, p + 1, ta.max_polls, ta.status);
-        for (int e = e0 + lane; e < e1; e += 64) sm.R[e] = pub_load(Ra + e);
+        // child a's rows of panel p: all loads issued before any is used
+        constexpr int IT = (e1 - e0 + 63) / 64;
+        T ra[IT];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int e = e0 + lane + 64 * u;
+            ra[u] = (e < e1) ? pub_load(Ra + e) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int e = e0 + lane + 64 * u;
+            if (e < e1) sm.R[e] = ra[u];
+        }
         if (!own_b) {
             typedef Mfma<T> M;
             const int l16 = lane & 15, l4 = lane >> 4;
@@ -788,7 +861,7 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
     if (lev == g.levels && ta.Rout) r_out<T, NP>(sm, n, rout_of<T>(ta, i0 / g.cpm), ta.ldr, ta.zero_lower != 0);
 }
 
-template <typename T, int NP, int SG, bool PIPE = false, bool WQ = true>
+template <typename T, int NP, int SG, bool PIPE = false, bool WQ = true, bool CHAIN = true>
 __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ A, int64_t lda,
                                           T* __restrict__ tau_blk, T* __restrict__ T_blk, T* __restrict__ Rbuf,
                                           T* __restrict__ Ynode, T* __restrict__ Tnode, T* __restrict__ tau_node,
@@ -796,33 +869,41 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
     const int n = (int)g.n;
     const int64_t tri = (int64_t)n * (n + 1) / 2;
     const int64_t nn = (int64_t)n * n;
-    // R starts at zero, so its entries beyond column n stay zero
-    for (int e = lane_id(); e < (int)(sizeof(sm.R) / sizeof(T)); e += 64) sm.R[e] = T(0);
-    wave_sync();
-    // ---- the chain (flat tree)
-    {
+    if constexpr (!CHAIN) {
+        // the chain was reduced by another launch: its R is in Rbuf
+        r_get<T, NP>(sm, Rbuf + (int64_t)c * rslot<NP>(n));
+    } else {
+        // R starts at zero, so its entries beyond column n stay zero
+        for (int e = lane_id(); e < (int)(sizeof(sm.R) / sizeof(T)); e += 64) sm.R[e] = T(0);
+        wave_sync();
+        // ---- the chain (flat tree)
         const int64_t start = chain_start(g, c), end = chain_end(g, c);
         const int nb = chain_nblocks(g, c);
         const int64_t blk0 = chain_blk0(g, c);
         constexpr int H = 16 * SG;
-        // The next block is loaded as soon as this block's reflectors are
-        // stored, so its loads are in flight during the T products.
+        // Each column tile is stored as soon as its panel is done, and the
+        // next block's tile is loaded into its registers as soon as they are
+        // free (right after the panel without an implicit Q, else during the
+        // T products), so the block's HBM traffic is spread over its work.
         T x[SG][4][NP];
         wload<T, NP, SG>(x, A, lda, start, (int)((end - start) < H ? (end - start) : H), n);
         for (int b = 0; b < nb; ++b) {
             const int64_t r0 = start + (int64_t)b * H;
             const int rows = (int)((end - r0) < H ? (end - r0) : H);
-            auto emit = [&]() {
-                wstore<T, NP, SG>(x, A, lda, r0, rows, n);
-                if (b + 1 < nb) {
-                    const int64_t r1 = r0 + H;
-                    wload<T, NP, SG>(x, A, lda, r1, (int)((end - r1) < H ? (end - r1) : H), n);
-                }
+            const int64_t r1 = r0 + H;
+            const int rows1 = (int)((end - r1) < H ? (end - r1) : H);
+            const bool more = b + 1 < nb;
+            auto done = [&](auto pc) { wstore_tile<T, NP, SG, decltype(pc)::value>(x, A, lda, r0, rows, n); };
+            auto free_ = [&](auto pc) {
+                if (more) wload_tile<T, NP, SG, decltype(pc)::value>(x, A, lda, r1, rows1, n);
             };
+            auto emit = [] {};
             if (b == 0)
-                wave_block<T, NP, SG, 0, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+                wave_block<T, NP, SG, 0, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit,
+                                             NoHook{}, NoHook{}, done, free_);
             else
-                wave_block<T, NP, SG, 1, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit);
+                wave_block<T, NP, SG, 1, WQ>(x, sm, n, T_blk + (blk0 + b) * tri, tau_blk + (blk0 + b) * n, emit,
+                                             NoHook{}, NoHook{}, done, free_);
         }
     }
     // ---- the tree

@@ -135,20 +135,21 @@ class QTree:
 
 
 def factor(A: torch.Tensor, R: torch.Tensor | None = None, block_rows=0, chains=0, arity=0,
-           levelwise: bool = False, want_q: bool = True, max_polls: int = 0):
+           levelwise: bool = False, want_q: bool = True, max_polls: int = 0, one_wave: bool = False):
     """TSQR of A (m x n, m >= n, n <= 64), IN PLACE: A is overwritten by the
     leaf reflectors.  Returns (R, QTree); diag(R) carries the Householder
     signs (see sign_normalize).  levelwise: reduce the tree node by node
     (TSQR_FLAG_TREE_LEVELWISE) instead of panel-pipelined; same result.
     want_q=False: R only (no implicit Q is formed); returns (R, None).
     max_polls: bound of the pipelined tree's waits (tsqr_opts.max_polls;
-    0 = the library default), for tests of the give-up path."""
+    0 = the library default), for tests of the give-up path.  one_wave:
+    TSQR_FLAG_ONE_WAVE (the one-wave chain engine everywhere; same bits)."""
     lib = _lib.load()
     m, n = A.shape
     if R is None:
         R = torch.empty(n, n, dtype=A.dtype, device=A.device)
     h = ctypes.c_void_p()
-    flags = _lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0
+    flags = (_lib.TSQR_FLAG_TREE_LEVELWISE if levelwise else 0) | (_lib.TSQR_FLAG_ONE_WAVE if one_wave else 0)
     rc = lib.tsqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), _ptr(R), _ld(R),
                          _opts(block_rows, chains, arity, flags, max_polls), ctypes.byref(h) if want_q else None,
                          _stream(A))
