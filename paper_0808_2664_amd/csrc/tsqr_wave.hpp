@@ -90,13 +90,13 @@ __device__ __forceinline__ T sum4(T x) {
 template <int J>
 __device__ __forceinline__ double bcast16(double x) {
     long long v = __builtin_bit_cast(long long, x);
-    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);
+    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, true);
     return __builtin_bit_cast(double, v);
 }
 template <int J>
 __device__ __forceinline__ float bcast16(float x) {
     int v = __builtin_bit_cast(int, x);
-    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);
+    v = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, true);
     return __builtin_bit_cast(float, v);
 }
 // Value of lane L (wave-uniform).
@@ -125,6 +125,102 @@ __device__ __forceinline__ int opaque_s(int v) {
     asm volatile("" : "+s"(v));
     return v;
 }
+
+// ---- FMA with a broadcast operand -----------------------------------------------
+// The column sweep multiplies every value of a lane by the value of column jj
+// in the same row (DPP row_newbcast).  The compiler emits the broadcast as a
+// separate move for 64-bit operands; v_fmac with a DPP source does both in
+// one instruction.  These are written out here for the unmasked row groups
+// [0, NS) of one panel tile x[.][.][L]:
+//   dot_bc:  a[i] += bcast(x[s][i]) * x[s][i]   (s ascending; the sums of the
+//            plain code, bit for bit)
+//   upd_bc:  x[s][i] += bcast(x[s][i]) * coef   (in place: lane J of each row
+//            has coef = 0, so the value it broadcasts is the same before and
+//            after the write)
+// Hazards the compiler does not see through inline asm are covered by the
+// leading s_nop: a DPP read needs 2 wait states after a VALU write of any of
+// its VGPRs and 5 after an EXEC write; the first column of a sweep (GUARD)
+// follows the block-reflector products, whose MFMA results need 18 before a
+// VALU reads them.  Inside one statement an accumulator is rewritten every
+// fourth instruction (>= 2 wait states).  Every value written here is
+// rewritten by compiler-visible VALU code (the sweep's final scaling) before
+// an MFMA or a store reads it.
+#define TSQR_DPP " row_newbcast:%c[J] row_mask:0xf bank_mask:0xf\n\t"
+#define TSQR_NOP_GUARD "s_nop 7\n\ts_nop 7\n\ts_nop 7\n\t"
+#define TSQR_NOP "s_nop 4\n\t"
+#define TSQR_DOT4(OP, s) \
+    OP " %[a0], %[x" #s "0], %[x" #s "0]" TSQR_DPP OP " %[a1], %[x" #s "1], %[x" #s "1]" TSQR_DPP \
+    OP " %[a2], %[x" #s "2], %[x" #s "2]" TSQR_DPP OP " %[a3], %[x" #s "3], %[x" #s "3]" TSQR_DPP
+#define TSQR_UPD4(OP, s) \
+    OP " %[x" #s "0], %[x" #s "0], %[cf]" TSQR_DPP OP " %[x" #s "1], %[x" #s "1], %[cf]" TSQR_DPP \
+    OP " %[x" #s "2], %[x" #s "2], %[cf]" TSQR_DPP OP " %[x" #s "3], %[x" #s "3], %[cf]" TSQR_DPP
+#define TSQR_XI(s, L) \
+    [x##s##0] "v"(x[s][0][L]), [x##s##1] "v"(x[s][1][L]), [x##s##2] "v"(x[s][2][L]), [x##s##3] "v"(x[s][3][L])
+#define TSQR_XO(s, L) \
+    [x##s##0] "+v"(x[s][0][L]), [x##s##1] "+v"(x[s][1][L]), [x##s##2] "+v"(x[s][2][L]), [x##s##3] "+v"(x[s][3][L])
+#define TSQR_ACC [a0] "+v"(a[0]), [a1] "+v"(a[1]), [a2] "+v"(a[2]), [a3] "+v"(a[3])
+
+#define TSQR_DOT_BODY(OP, NOPS)                                                                                    \
+    if constexpr (NS == 1)                                                                                         \
+        asm(NOPS TSQR_DOT4(OP, 0) : TSQR_ACC : TSQR_XI(0, L), [J] "n"(J));                                         \
+    else if constexpr (NS == 2)                                                                                    \
+        asm(NOPS TSQR_DOT4(OP, 0) TSQR_DOT4(OP, 1) : TSQR_ACC : TSQR_XI(0, L), TSQR_XI(1, L), [J] "n"(J));        \
+    else if constexpr (NS == 3)                                                                                    \
+        asm(NOPS TSQR_DOT4(OP, 0) TSQR_DOT4(OP, 1) TSQR_DOT4(OP, 2)                                               \
+            : TSQR_ACC : TSQR_XI(0, L), TSQR_XI(1, L), TSQR_XI(2, L), [J] "n"(J));                                 \
+    else                                                                                                           \
+        asm(NOPS TSQR_DOT4(OP, 0) TSQR_DOT4(OP, 1) TSQR_DOT4(OP, 2) TSQR_DOT4(OP, 3)                              \
+            : TSQR_ACC : TSQR_XI(0, L), TSQR_XI(1, L), TSQR_XI(2, L), TSQR_XI(3, L), [J] "n"(J));
+#define TSQR_UPD_BODY(OP)                                                                                          \
+    if constexpr (NS == 1)                                                                                         \
+        asm(TSQR_NOP TSQR_UPD4(OP, 0) : TSQR_XO(0, L) : [cf] "v"(coef), [J] "n"(J));                               \
+    else if constexpr (NS == 2)                                                                                    \
+        asm(TSQR_NOP TSQR_UPD4(OP, 0) TSQR_UPD4(OP, 1) : TSQR_XO(0, L), TSQR_XO(1, L) : [cf] "v"(coef), [J] "n"(J)); \
+    else if constexpr (NS == 3)                                                                                    \
+        asm(TSQR_NOP TSQR_UPD4(OP, 0) TSQR_UPD4(OP, 1) TSQR_UPD4(OP, 2)                                           \
+            : TSQR_XO(0, L), TSQR_XO(1, L), TSQR_XO(2, L) : [cf] "v"(coef), [J] "n"(J));                           \
+    else                                                                                                           \
+        asm(TSQR_NOP TSQR_UPD4(OP, 0) TSQR_UPD4(OP, 1) TSQR_UPD4(OP, 2) TSQR_UPD4(OP, 3)                          \
+            : TSQR_XO(0, L), TSQR_XO(1, L), TSQR_XO(2, L), TSQR_XO(3, L) : [cf] "v"(coef), [J] "n"(J));
+
+template <int J, int NS, int L, bool GUARD, int SGX, int NPX>
+__device__ __forceinline__ void dot_bc(double (&a)[4], const double (&x)[SGX][4][NPX]) {
+    static_assert(NS >= 1 && NS <= SGX && SGX <= 4, "row groups");
+    if constexpr (GUARD) {
+        TSQR_DOT_BODY("v_fmac_f64_dpp", TSQR_NOP_GUARD)
+    } else {
+        TSQR_DOT_BODY("v_fmac_f64_dpp", TSQR_NOP)
+    }
+}
+template <int J, int NS, int L, bool GUARD, int SGX, int NPX>
+__device__ __forceinline__ void dot_bc(float (&a)[4], const float (&x)[SGX][4][NPX]) {
+    static_assert(NS >= 1 && NS <= SGX && SGX <= 4, "row groups");
+    if constexpr (GUARD) {
+        TSQR_DOT_BODY("v_fmac_f32_dpp", TSQR_NOP_GUARD)
+    } else {
+        TSQR_DOT_BODY("v_fmac_f32_dpp", TSQR_NOP)
+    }
+}
+template <int J, int NS, int L, int SGX, int NPX>
+__device__ __forceinline__ void upd_bc(double (&x)[SGX][4][NPX], double coef) {
+    static_assert(NS >= 1 && NS <= SGX && SGX <= 4, "row groups");
+    TSQR_UPD_BODY("v_fmac_f64_dpp")
+}
+template <int J, int NS, int L, int SGX, int NPX>
+__device__ __forceinline__ void upd_bc(float (&x)[SGX][4][NPX], float coef) {
+    static_assert(NS >= 1 && NS <= SGX && SGX <= 4, "row groups");
+    TSQR_UPD_BODY("v_fmac_f32_dpp")
+}
+#undef TSQR_DOT_BODY
+#undef TSQR_UPD_BODY
+#undef TSQR_ACC
+#undef TSQR_XO
+#undef TSQR_XI
+#undef TSQR_UPD4
+#undef TSQR_DOT4
+#undef TSQR_NOP
+#undef TSQR_NOP_GUARD
+#undef TSQR_DPP
 
 // Order this wave's LDS (and global) accesses across its lanes.
 __device__ __forceinline__ void wave_sync() {
@@ -276,16 +372,20 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             // four running sums (one per register of a row group), so the
             // dependent chain is one FMA per row group
             T acc4[4] = {T(0), T(0), T(0), T(0)};
-            sfor<S0, S1>([&](auto sc) {
-                constexpr int s = decltype(sc)::value;
+            if constexpr (MODE == 0) {
+                sfor<S0, S1>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    T v = bcast16<jj>(x[s][i][p]);
-                    if constexpr (MODE == 0 && s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
-                    xj[s][i] = v;
-                    acc4[i] = fma(v, x[s][i][p], acc4[i]);
-                }
-            });
+                    for (int i = 0; i < 4; ++i) {
+                        T v = bcast16<jj>(x[s][i][p]);
+                        if constexpr (s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
+                        xj[s][i] = v;
+                        acc4[i] = fma(v, x[s][i][p], acc4[i]);
+                    }
+                });
+            } else {
+                dot_bc<jj, S1, p, jj == 0>(acc4, x);
+            }
             const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
             const T sigma2 = bcast16<jj>(g);
             T beta, tau, scale;
@@ -304,11 +404,15 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
                 T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&sm.scr[0][0] + l16);
                 *dst = (c == j) ? beta : hc - tw;
             }
-            sfor<S0, S1>([&](auto sc) {
-                constexpr int s = decltype(sc)::value;
+            if constexpr (MODE == 0) {
+                sfor<S0, S1>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) x[s][i][p] = fma(xj[s][i], coef, x[s][i][p]);
-            });
+                    for (int i = 0; i < 4; ++i) x[s][i][p] = fma(xj[s][i], coef, x[s][i][p]);
+                });
+            } else {
+                upd_bc<jj, S1, p>(x, coef);
+            }
             if constexpr (MODE == 0) {
                 T& hv = x[p][hreg][p];
                 const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);

@@ -16,6 +16,12 @@
 // SIMD (two waves per SIMD), where the one-wave engine (tsqr_wave.hpp) runs
 // one latency-bound column sweep at a time.
 //
+// Wave B carries five of the six block-reflector updates of a block, wave A
+// one, so with the implicit Q kept the off-diagonal blocks of T (Gram blocks
+// V_a^T V_c and the T recurrence) go to wave A: once wave B has published a
+// block (its reflectors in HBM, its diagonal T blocks in LDS), wave A forms
+// that block's off-diagonal T blocks between two blocks of its own.
+//
 // Every step is the arithmetic of the one-wave engine on a column subset:
 // the same reflectors (Sec. 5.2 convention), the same compact form
 // I - V T V^T per block (T upper triangular, forward product), the same
@@ -35,10 +41,10 @@ struct W2Smem {
     T R[RP];                     // the chain's R (packed by rows); columns 0..31 wave A's, 32..63 wave B's
     T scr[2][16][17];            // per-wave transposes and the sweep's staging target
     T tdA[kW2Ring][2][16][17];   // wave A's diagonal T blocks (panels 0, 1), one slot per block in flight
-    T tdB[2][16][17];            // wave B's diagonal T blocks (panels 2, 3)
-    T p01[kW2Ring][4][64];       // wave A's Gram block V_0^T V_1 (A-operand layout, per lane) per slot
+    T tdB[kW2Ring][2][16][17];   // wave B's diagonal T blocks (panels 2, 3), one slot per block in flight
     int ready;                   // blocks whose panels 0 and 1 wave A has published
-    int used;                    // blocks whose slot wave B has released
+    int used;                    // blocks whose slot wave B has released (R only)
+    int swept;                   // blocks wave B has published (implicit Q kept)
 };
 
 // LDS flag helpers (workgroup scope).
@@ -160,16 +166,20 @@ __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&sc
         }
         T xj[SG][4];
         T acc4[4] = {T(0), T(0), T(0), T(0)};
-        sfor<S0, SG>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
+        if constexpr (MODE == 0) {
+            sfor<S0, SG>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                T v = bcast16<jj>(x[s][i][lt]);
-                if constexpr (MODE == 0 && s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
-                xj[s][i] = v;
-                acc4[i] = fma(v, x[s][i][lt], acc4[i]);
-            }
-        });
+                for (int i = 0; i < 4; ++i) {
+                    T v = bcast16<jj>(x[s][i][lt]);
+                    if constexpr (s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
+                    xj[s][i] = v;
+                    acc4[i] = fma(v, x[s][i][lt], acc4[i]);
+                }
+            });
+        } else {
+            dot_bc<jj, SG, lt, jj == 0>(acc4, x);
+        }
         const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
         const T sigma2 = bcast16<jj>(g);
         T beta, tau, scale;
@@ -187,11 +197,15 @@ __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&sc
             T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&scr[0][0] + l16);
             *dst = (c == j) ? beta : hc - tw;
         }
-        sfor<S0, SG>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
+        if constexpr (MODE == 0) {
+            sfor<S0, SG>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x[s][i][lt] = fma(xj[s][i], coef, x[s][i][lt]);
-        });
+                for (int i = 0; i < 4; ++i) x[s][i][lt] = fma(xj[s][i], coef, x[s][i][lt]);
+            });
+        } else {
+            upd_bc<jj, SG, lt>(x, coef);
+        }
         if constexpr (MODE == 0) {
             T& hv = x[p][hreg][lt];
             const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);
@@ -406,6 +420,81 @@ __device__ __forceinline__ void w2_tstore(T* __restrict__ Tout, int a, int b, co
         if (jx < n) Tout[tpi(16 * a + M::orow(l4, r), jx)] = t[r];
 }
 
+// Off-diagonal blocks of one block's T (wave A, after wave B published the
+// block): T_ab = -T_aa sum_{c=a+1..b} P_ac T_cb for b = 1..3, a = b-1..0,
+// with the Gram blocks P_ac = V_a^T V_c of the four reflector tiles read back
+// from HBM and the diagonal blocks from the block's LDS slot.
+template <typename T, int SG, int MODE>
+__device__ __forceinline__ void w2_tblocks(W2Smem<T>& sm, const T* __restrict__ A, int64_t lda, int64_t r0, int rows,
+                                           int n, int slot, T* __restrict__ Tout) {
+    typedef Mfma<T> M;
+    typedef typename M::acc acc_t;
+    acc_t P01, P02, P03, P12, P13, P23;
+    {
+        T v2[SG][4], v3[SG][4];
+        v_load_tile<T, SG, 2>(v2, A, lda, r0, rows, n);
+        v_load_tile<T, SG, 3>(v3, A, lda, r0, rows, n);
+        P23 = w2_gram<T, SG, MODE, 3>(v2, v3);
+        T v0[SG][4];
+        v_load_tile<T, SG, 0>(v0, A, lda, r0, rows, n);
+        P02 = w2_gram<T, SG, MODE, 2>(v0, v2);
+        P03 = w2_gram<T, SG, MODE, 3>(v0, v3);
+        T v1[SG][4];
+        v_load_tile<T, SG, 1>(v1, A, lda, r0, rows, n);
+        P01 = w2_gram<T, SG, MODE, 1>(v0, v1);
+        P12 = w2_gram<T, SG, MODE, 2>(v1, v2);
+        P13 = w2_gram<T, SG, MODE, 3>(v1, v3);
+    }
+    T tD0[4], tA0[4], tD1[4], tA1[4], tD2[4], tA2[4], tD3[4], tA3[4];
+    w2_tblock<T>(sm.tdA[slot][0], tD0, tA0);
+    w2_tblock<T>(sm.tdA[slot][1], tD1, tA1);
+    w2_tblock<T>(sm.tdB[slot][0], tD2, tA2);
+    w2_tblock<T>(sm.tdB[slot][1], tD3, tA3);
+    (void)tD0;
+    (void)tA3;
+    // column block 1
+    acc_t y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], tD1[kc], y);
+    const acc_t t01 = w2_tnext<T>(tA0, y);
+    w2_tstore<T>(Tout, 0, 1, t01, n);
+    // column block 2
+    y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P12[kc], tD2[kc], y);
+    const acc_t t12 = w2_tnext<T>(tA1, y);
+    y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], t12[kc], y);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P02[kc], tD2[kc], y);
+    const acc_t t02 = w2_tnext<T>(tA0, y);
+    w2_tstore<T>(Tout, 1, 2, t12, n);
+    w2_tstore<T>(Tout, 0, 2, t02, n);
+    // column block 3
+    y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P23[kc], tD3[kc], y);
+    const acc_t t23 = w2_tnext<T>(tA2, y);
+    w2_tstore<T>(Tout, 2, 3, t23, n);
+    y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P12[kc], t23[kc], y);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P13[kc], tD3[kc], y);
+    const acc_t t13 = w2_tnext<T>(tA1, y);
+    w2_tstore<T>(Tout, 1, 3, t13, n);
+    y = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], t13[kc], y);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P02[kc], t23[kc], y);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) y = M::mma(P03[kc], tD3[kc], y);
+    const acc_t t03 = w2_tnext<T>(tA0, y);
+    w2_tstore<T>(Tout, 0, 3, t03, n);
+}
+
 // One chain of the two-wave engine; the chain's R is left in sm.R (both
 // waves' columns complete when this returns, after a workgroup barrier).
 template <typename T, bool WQ>
@@ -422,6 +511,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
     if (threadIdx.x == 0) {
         sm.ready = 0;
         sm.used = 0;
+        sm.swept = 0;
     }
     __syncthreads();
     const int64_t start = chain_start(g, ch), end = chain_end(g, ch);
@@ -441,8 +531,9 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
             const int slot = b % kW2Ring;
             T* Tout = T_blk + (blk0 + b) * tri;
             T* tauout = tau_blk + (blk0 + b) * n;
-            // the slot's previous block must have been released by wave B
-            if (b >= kW2Ring) lds_wait_ge(&sm.used, b - kW2Ring + 1);
+            // the slot's previous block must have been released by wave B (with
+            // the implicit Q kept, wave A's wait for block b - 1 below implies it)
+            if (!WQ && b >= kW2Ring) lds_wait_ge(&sm.used, b - kW2Ring + 1);
             auto blockA = [&](auto mc) {
                 constexpr int MODE = decltype(mc)::value;
                 w2_sweep<T, SG, MODE, WQ, 0, 0>(x, sm, sm.scr[0], sm.tdA[slot][0], n, Tout, tauout);
@@ -465,36 +556,31 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                     wave_sync();
                 }
                 x_store_tile<T, SG, 0, 1>(x, A, lda, r0, rows, n);
-                if constexpr (WQ) {
-                    // T_01 = -T_00 (V_0^T V_1) T_11
-                    T v0[SG][4], v1[SG][4];
-#pragma unroll
-                    for (int s = 0; s < SG; ++s)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            v0[s][i] = x[s][i][0];
-                            v1[s][i] = x[s][i][1];
-                        }
-                    const acc_t P01 = w2_gram<T, SG, MODE, 1>(v0, v1);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) sm.p01[slot][r][lane] = P01[r];
-                    T tD0[4], tA0[4], tD1[4], tA1[4];
-                    w2_tblock<T>(sm.tdA[slot][0], tD0, tA0);
-                    w2_tblock<T>(sm.tdA[slot][1], tD1, tA1);
-                    acc_t y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], tD1[kc], y);
-                    const acc_t t01 = w2_tnext<T>(tA0, y);
-                    w2_tstore<T>(Tout, 0, 1, t01, n);
-                    (void)tD0;
-                }
-                // the tails are in HBM (L2) and P_01 in LDS before wave B is told
+                // the tails are in HBM (L2) before wave B is told
                 pub_wait();
                 lds_store_rel(&sm.ready, b + 1);
             };
             if (b == 0) blockA(ic_t<0>{});
             else blockA(ic_t<1>{});
+            if constexpr (WQ) {
+                // the previous block's off-diagonal T blocks, once wave B has published it
+                if (b >= 1) {
+                    lds_wait_ge(&sm.swept, b);
+                    const int pb = b - 1;
+                    T* Tprev = T_blk + (blk0 + pb) * tri;
+                    if (pb == 0) w2_tblocks<T, SG, 0>(sm, A, lda, r0 - H, rows_of(pb), n, pb % kW2Ring, Tprev);
+                    else w2_tblocks<T, SG, 1>(sm, A, lda, r0 - H, rows_of(pb), n, pb % kW2Ring, Tprev);
+                }
+            }
             if (b + 1 < nb) x_load_tiles<T, SG, 0>(x, A, lda, r0 + H, rows_of(b + 1), n);
+        }
+        if (WQ && nb > 0) {
+            lds_wait_ge(&sm.swept, nb);
+            const int pb = nb - 1;
+            T* Tprev = T_blk + (blk0 + pb) * tri;
+            const int64_t rp = start + (int64_t)pb * H;
+            if (pb == 0) w2_tblocks<T, SG, 0>(sm, A, lda, rp, rows_of(pb), n, pb % kW2Ring, Tprev);
+            else w2_tblocks<T, SG, 1>(sm, A, lda, rp, rows_of(pb), n, pb % kW2Ring, Tprev);
         }
     } else {
         // ---------------------------------------------------------------- wave B
@@ -526,7 +612,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                 if constexpr (!WQ) lds_store_rel(&sm.used, b + 1);
                 // panels 2 and 3 (columns beyond n are zero: no skip needed
                 // past panel 2, which n > 32 reaches)
-                w2_sweep<T, SG, MODE, WQ, 2, 2>(x, sm, sm.scr[1], sm.tdB[0], n, Tout, tauout);
+                w2_sweep<T, SG, MODE, WQ, 2, 2>(x, sm, sm.scr[1], sm.tdB[slot][0], n, Tout, tauout);
                 x_store_tile<T, SG, 2, 0>(x, A, lda, r0, rows, n);
                 {
                     T v2[SG][4];
@@ -534,96 +620,22 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                     for (int s = 0; s < SG; ++s)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) v2[s][i] = x[s][i][0];
-                    w2_apply<T, SG, MODE, 2, 2, 3>(x, v2, sm, sm.scr[1], sm.tdB[0], n);
+                    w2_apply<T, SG, MODE, 2, 2, 3>(x, v2, sm, sm.scr[1], sm.tdB[slot][0], n);
                 }
                 if constexpr (MODE == 0) w2_rows_to_r<T, SG, 2, 2>(x, sm, n);
                 if (48 < n) {
-                    w2_sweep<T, SG, MODE, WQ, 2, 3>(x, sm, sm.scr[1], sm.tdB[1], n, Tout, tauout);
+                    w2_sweep<T, SG, MODE, WQ, 2, 3>(x, sm, sm.scr[1], sm.tdB[slot][1], n, Tout, tauout);
                     if constexpr (MODE == 0) w2_rows_to_r<T, SG, 2, 3>(x, sm, n);
                 } else {
-                    for (int e = lane; e < 16 * 17; e += 64) (&sm.tdB[1][0][0])[e] = T(0);
+                    for (int e = lane; e < 16 * 17; e += 64) (&sm.tdB[slot][1][0][0])[e] = T(0);
                     wave_sync();
                 }
                 x_store_tile<T, SG, 2, 1>(x, A, lda, r0, rows, n);
                 if constexpr (WQ) {
-                    // T blocks of columns 2 and 3: T_ab = -T_aa sum_{c=a+1..b} P_ac T_cb
-                    T v2[SG][4], v3[SG][4];
-#pragma unroll
-                    for (int s = 0; s < SG; ++s)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            v2[s][i] = x[s][i][0];
-                            v3[s][i] = x[s][i][1];
-                        }
-                    const acc_t P23 = w2_gram<T, SG, MODE, 3>(v2, v3);
-                    acc_t P02, P03, P12, P13;
-                    {
-                        T va[SG][4];
-                        v_load_tile<T, SG, 0>(va, A, lda, r0, rows, n);
-                        P02 = w2_gram<T, SG, MODE, 2>(va, v2);
-                        P03 = w2_gram<T, SG, MODE, 3>(va, v3);
-                    }
-                    {
-                        T vb[SG][4];
-                        v_load_tile<T, SG, 1>(vb, A, lda, r0, rows, n);
-                        P12 = w2_gram<T, SG, MODE, 2>(vb, v2);
-                        P13 = w2_gram<T, SG, MODE, 3>(vb, v3);
-                    }
-                    acc_t P01;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) P01[r] = sm.p01[slot][r][lane];
-                    // column block 2
-                    acc_t t12, t02;
-                    {
-                        T tD2[4], tA2[4], tD1[4], tA1[4], tD0[4], tA0[4];
-                        w2_tblock<T>(sm.tdB[0], tD2, tA2);
-                        w2_tblock<T>(sm.tdA[slot][1], tD1, tA1);
-                        w2_tblock<T>(sm.tdA[slot][0], tD0, tA0);
-                        acc_t y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P12[kc], tD2[kc], y);
-                        t12 = w2_tnext<T>(tA1, y);
-                        y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], t12[kc], y);
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P02[kc], tD2[kc], y);
-                        t02 = w2_tnext<T>(tA0, y);
-                        w2_tstore<T>(Tout, 1, 2, t12, n);
-                        w2_tstore<T>(Tout, 0, 2, t02, n);
-                    }
-                    // column block 3
-                    {
-                        T tD3[4], tA3[4], tD2[4], tA2[4];
-                        w2_tblock<T>(sm.tdB[1], tD3, tA3);
-                        w2_tblock<T>(sm.tdB[0], tD2, tA2);
-                        acc_t y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P23[kc], tD3[kc], y);
-                        const acc_t t23 = w2_tnext<T>(tA2, y);
-                        w2_tstore<T>(Tout, 2, 3, t23, n);
-                        T tD1[4], tA1[4];
-                        w2_tblock<T>(sm.tdA[slot][1], tD1, tA1);
-                        y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P12[kc], t23[kc], y);
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P13[kc], tD3[kc], y);
-                        const acc_t t13 = w2_tnext<T>(tA1, y);
-                        w2_tstore<T>(Tout, 1, 3, t13, n);
-                        T tD0[4], tA0[4];
-                        w2_tblock<T>(sm.tdA[slot][0], tD0, tA0);
-                        y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P01[kc], t13[kc], y);
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P02[kc], t23[kc], y);
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) y = M::mma(P03[kc], tD3[kc], y);
-                        const acc_t t03 = w2_tnext<T>(tA0, y);
-                        w2_tstore<T>(Tout, 0, 3, t03, n);
-                    }
-                    lds_store_rel(&sm.used, b + 1);
+                    // tails in HBM (L2), diagonal T blocks in LDS: wave A may form
+                    // this block's off-diagonal T blocks
+                    pub_wait();
+                    lds_store_rel(&sm.swept, b + 1);
                 }
             };
             if (b == 0) blockB(ic_t<0>{});
