@@ -231,39 +231,46 @@ __device__ __forceinline__ void wave_sync() {
 // Householder scalars from alpha and sigma^2 = ||tail||^2 (valid for
 // sigma^2 > 0; the caller replaces them when sigma^2 == 0):
 // nrm = sqrt(alpha^2 + sigma^2), beta = -sign(alpha) nrm (sign(0) = +1),
-// tau = (beta - alpha)/beta = 1 + |alpha|/nrm, scale = 1/(alpha - beta).
-// Hardware reciprocal / reciprocal square root refined by Newton steps.
-__device__ __forceinline__ void hh_scalars(double alpha, double sigma2, double& beta, double& tau, double& scale) {
+// tau = (beta - alpha)/beta = 1 + |alpha|/nrm, scale = 1/(alpha - beta), and
+// rbeta = 1/beta = -tau * scale, the factor that takes v^T x to the update
+// coefficient of the scaled tail (-tau (v^T x) scale).
+// The hardware reciprocal square root and reciprocal are refined by one
+// third-order step each, y0 (1 + e/2 + 3e^2/8) with e = 1 - s y0^2 and
+// r0 (1 + e + e^2) with e = 1 - d r0 (from about 22 correct bits to full
+// precision; fewer dependent operations than two Newton steps, and this
+// chain is the latency of every column of the sweep).  alpha - beta never
+// cancels: both terms carry the sign of alpha.
+__device__ __forceinline__ void hh_scalars(double alpha, double sigma2, double& beta, double& tau, double& scale,
+                                           double& rbeta) {
     const double s = fma(alpha, alpha, sigma2);
-    double y = __builtin_amdgcn_rsq(s);
-    double e = fma(-s * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-s * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
+    const double y0 = __builtin_amdgcn_rsq(s);
+    const double e = fma(-s * y0, y0, 1.0);
+    const double y = fma(y0, e * fma(e, 0.375, 0.5), y0);
     double nrm = s * y;
     nrm = fma(fma(-nrm, nrm, s), 0.5 * y, nrm);
-    const double aa = fabs(alpha);
-    beta = (alpha >= 0.0) ? -nrm : nrm;
-    tau = fma(aa, y, 1.0);
-    const double d = aa + nrm;
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
-    scale = (alpha >= 0.0) ? r : -r;
+    const bool pos = alpha >= 0.0;
+    beta = pos ? -nrm : nrm;
+    rbeta = pos ? -y : y;
+    tau = fma(fabs(alpha), y, 1.0);
+    const double d = alpha - beta;
+    const double r0 = __builtin_amdgcn_rcp(d);
+    const double e2 = fma(-d, r0, 1.0);
+    scale = fma(r0, fma(e2, e2, e2), r0);
 }
-__device__ __forceinline__ void hh_scalars(float alpha, float sigma2, float& beta, float& tau, float& scale) {
+__device__ __forceinline__ void hh_scalars(float alpha, float sigma2, float& beta, float& tau, float& scale,
+                                           float& rbeta) {
     const float s = fmaf(alpha, alpha, sigma2);
     float y = __builtin_amdgcn_rsqf(s);
     y = fmaf(0.5f * y, fmaf(-s * y, y, 1.0f), y);
     float nrm = s * y;
     nrm = fmaf(fmaf(-nrm, nrm, s), 0.5f * y, nrm);
-    const float aa = fabsf(alpha);
-    beta = (alpha >= 0.0f) ? -nrm : nrm;
-    tau = fmaf(aa, y, 1.0f);
-    const float d = aa + nrm;
+    const bool pos = alpha >= 0.0f;
+    beta = pos ? -nrm : nrm;
+    rbeta = pos ? -y : y;
+    tau = fmaf(fabsf(alpha), y, 1.0f);
+    const float d = alpha - beta;
     float r = __builtin_amdgcn_rcpf(d);
-    r = fmaf(r, fmaf(-d, r, 1.0f), r);
-    scale = (alpha >= 0.0f) ? r : -r;
+    scale = fmaf(r, fmaf(-d, r, 1.0f), r);
 }
 
 // ---- per-wave LDS -------------------------------------------------------------
@@ -343,6 +350,24 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
         constexpr int S1 = (MODE == 2) ? p + 1 : SG;
         const int c = c0 + l16;
         T sc_lane = T(1), tau_lane = T(0);
+        // in-panel Gram P[c][k] = v_c^T v_k (lanes c < k) and column k of the
+        // panel's T (row l16 per lane group, kept in sm.td[p]):
+        // T[a][k] = -tau_k sum_{i<k} T[a][i] P[i][k], T[k][k] = tau_k (two
+        // running sums over i, so the sum is not one dependent chain).  Formed
+        // one column late, inside the next column's step, where it overlaps
+        // that column's reduction and Householder scalars.
+        T pw_prev = T(0), tau_prev = T(0);
+        auto tcol = [&](auto kc_) {
+            constexpr int k = decltype(kc_)::value;
+            const int l16 = lane_id() & 15;
+            T tk[2] = {T(0), T(0)};
+            sfor<0, k>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                tk[i & 1] = fma(sm.td[p][l16][i], bcast16<i>(pw_prev), tk[i & 1]);
+            });
+            const T t = tk[0] + tk[1];
+            sm.td[p][l16][k] = (l16 < k) ? -tau_prev * t : ((l16 == k) ? tau_prev : T(0));
+        };
 
         // ------------------------------------------------------ column sweep
         sfor<0, 16>([&](auto jc) {
@@ -386,18 +411,22 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             } else {
                 dot_bc<jj, S1, p, jj == 0>(acc4, x);
             }
+            if constexpr (jj > 0) tcol(ic_t<jj - 1>{});
             const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
             const T sigma2 = bcast16<jj>(g);
             T beta, tau, scale;
-            hh_scalars(alpha, sigma2, beta, tau, scale);
+            T rbeta;
+            hh_scalars(alpha, sigma2, beta, tau, scale, rbeta);
             const bool zt = (sigma2 == T(0));
             tau = zt ? T(0) : tau;
             scale = zt ? T(0) : scale;
             beta = zt ? alpha : beta;
-            const T w = fma(scale, g, hc);
             const bool trail = (c > j) && (c < n);
+            // coef = -tau w scale = w / beta, its factor selected off the critical path
+            const T mcoef = (trail && !zt) ? rbeta : T(0);
+            const T w = fma(scale, g, hc);
             const T tw = tau * w;
-            const T coef = trail ? -tw * scale : T(0);
+            const T coef = w * mcoef;
             if constexpr (MODE != 0) {
                 // every lane stores (the four lanes of a column hold the same
                 // value); lanes left of the diagonal write into the staging tile
@@ -421,19 +450,10 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
             // lane jj keeps its column unscaled until the panel ends (sc_lane)
             sc_lane = (l16 == jj) ? scale : sc_lane;
             tau_lane = (l16 == jj) ? tau : tau_lane;
-            // in-panel Gram P[c][j] = v_c^T v_j (lanes c < j) and column j of the
-            // panel's T (row l16 per lane group, kept in sm.td[p]):
-            // T[a][j] = -tau_j sum_{k<j} T[a][k] P[k][j], T[j][j] = tau_j
-            // (two running sums over k, so the sum is not one dependent chain)
-            const T pw = sc_lane * w;
-            T tk[2] = {T(0), T(0)};
-            sfor<0, jj>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                tk[k & 1] = fma(sm.td[p][l16][k], bcast16<k>(pw), tk[k & 1]);
-            });
-            const T t = tk[0] + tk[1];
-            sm.td[p][l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
+            pw_prev = sc_lane * w;
+            tau_prev = tau;
         });
+        tcol(ic_t<15>{});
 
         // reflector tails: scale the panel's columns (delayed from the sweep)
         sfor<S0, S1>([&](auto sc) {

@@ -144,6 +144,21 @@ __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&sc
     const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
     const int c = c0 + l16;
     T sc_lane = T(1), tau_lane = T(0);
+    // column k of the panel's T: T[a][k] = -tau_k sum_{i<k} T[a][i] (v_i^T v_k),
+    // formed one column late, inside the next column's step, where it overlaps
+    // that column's reduction and Householder scalars
+    T pw_prev = T(0), tau_prev = T(0);
+    auto tcol = [&](auto kc_) {
+        constexpr int k = decltype(kc_)::value;
+        const int l16 = lane_id() & 15;
+        T tk[2] = {T(0), T(0)};
+        sfor<0, k>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            tk[i & 1] = fma(td[l16][i], bcast16<i>(pw_prev), tk[i & 1]);
+        });
+        const T t = tk[0] + tk[1];
+        td[l16][k] = (l16 < k) ? -tau_prev * t : ((l16 == k) ? tau_prev : T(0));
+    };
     sfor<0, 16>([&](auto jc) {
         constexpr int jj = decltype(jc)::value;
         // columns j >= n are zero: the arithmetic leaves the tile unchanged
@@ -180,18 +195,22 @@ __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&sc
         } else {
             dot_bc<jj, SG, lt, jj == 0>(acc4, x);
         }
+        if constexpr (jj > 0) tcol(ic_t<jj - 1>{});
         const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
         const T sigma2 = bcast16<jj>(g);
         T beta, tau, scale;
-        hh_scalars(alpha, sigma2, beta, tau, scale);
+        T rbeta;
+        hh_scalars(alpha, sigma2, beta, tau, scale, rbeta);
         const bool zt = (sigma2 == T(0));
         tau = zt ? T(0) : tau;
         scale = zt ? T(0) : scale;
         beta = zt ? alpha : beta;
-        const T w = fma(scale, g, hc);
         const bool trail = (c > j) && (c < n);
+        // coef = -tau w scale = w / beta, its factor selected off the critical path
+        const T mcoef = (trail && !zt) ? rbeta : T(0);
+        const T w = fma(scale, g, hc);
         const T tw = tau * w;
-        const T coef = trail ? -tw * scale : T(0);
+        const T coef = w * mcoef;
         if constexpr (MODE != 0) {
             // every lane stores; lanes left of the diagonal write into the staging tile
             T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&scr[0][0] + l16);
@@ -213,16 +232,10 @@ __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&sc
         }
         sc_lane = (l16 == jj) ? scale : sc_lane;
         tau_lane = (l16 == jj) ? tau : tau_lane;
-        // column jj of the panel's T: T[a][j] = -tau_j sum_{k<j} T[a][k] (v_k^T v_j)
-        const T pw = sc_lane * w;
-        T tk[2] = {T(0), T(0)};
-        sfor<0, jj>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            tk[k & 1] = fma(td[l16][k], bcast16<k>(pw), tk[k & 1]);
-        });
-        const T t = tk[0] + tk[1];
-        td[l16][jj] = (l16 < jj) ? -tau * t : ((l16 == jj) ? tau : T(0));
+        pw_prev = sc_lane * w;
+        tau_prev = tau;
     });
+    tcol(ic_t<15>{});
     sfor<S0, SG>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
 #pragma unroll
