@@ -211,6 +211,23 @@ __device__ __forceinline__ void upd_bc(float (&x)[SGX][4][NPX], float coef) {
     static_assert(NS >= 1 && NS <= SGX && SGX <= 4, "row groups");
     TSQR_UPD_BODY("v_fmac_f32_dpp")
 }
+// acc += bcast(a)[lane J] * b, one term of a sum whose running sums
+// alternate: the leading wait states cover a VALU write of any operand one
+// instruction earlier (2) and, for the first term (FIRST), an EXEC write (5).
+template <int J, bool FIRST>
+__device__ __forceinline__ void fmac_bc(double& acc, double a, double b) {
+    if constexpr (FIRST)
+        asm("s_nop 4\n\tv_fmac_f64_dpp %0, %1, %2" TSQR_DPP : "+v"(acc) : "v"(a), "v"(b), [J] "n"(J));
+    else
+        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2" TSQR_DPP : "+v"(acc) : "v"(a), "v"(b), [J] "n"(J));
+}
+template <int J, bool FIRST>
+__device__ __forceinline__ void fmac_bc(float& acc, float a, float b) {
+    if constexpr (FIRST)
+        asm("s_nop 4\n\tv_fmac_f32_dpp %0, %1, %2" TSQR_DPP : "+v"(acc) : "v"(a), "v"(b), [J] "n"(J));
+    else
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2" TSQR_DPP : "+v"(acc) : "v"(a), "v"(b), [J] "n"(J));
+}
 #undef TSQR_DOT_BODY
 #undef TSQR_UPD_BODY
 #undef TSQR_ACC
@@ -279,8 +296,11 @@ struct WSmem {
     static constexpr int NCP = 16 * NP;
     static constexpr int RP = NCP * (NCP + 1) / 2;
     T R[RP];            // on-chip R, upper triangle packed by rows
-    T scr[16][17];      // transposes
-    T td[NP][16][17];   // diagonal T blocks of the panels (row l of block p in td[p][l])
+    T scr[16][17];      // transposes; the column sweep's sink for stores without a target
+    T td[NP][16][17];   // diagonal T blocks of the panels (row l of block p in td[p][l]);
+                        // entries below the diagonal stay zero
+    T scl[16];          // scales of the current panel's columns
+    T zero;             // holds 0
 };
 // Packed index of R[r][c], c >= r, rows of length NCP.
 template <int NCP>
@@ -297,6 +317,143 @@ __device__ __forceinline__ T vmask(T x, int r, int c) {
 
 // Packed-T index of T[i][j], i <= j (column by column).
 __device__ __forceinline__ int64_t tpi(int i, int j) { return (int64_t)j * (j + 1) / 2 + i; }
+
+// ---- the column sweep of one panel -------------------------------------------------
+//
+// Panel p (columns 16p .. 16p + 15) of a block held in x[.][.][L] (tile
+// layout), reduced column by column with one lane reduction per column:
+// g_c = sum over the tail rows of x_j x_c for every column c at once gives
+// sigma^2 = g_j and v_j^T x_c = head_c + scale_j g_c.  MODE 0: the heads lie
+// in the tile (row group p; row groups [p, SG) are live); otherwise the heads
+// are rows of the on-chip R (packed rows of NCP columns at R) and row groups
+// [0, S1) of the tile are live (a tree node's lower triangle has S1 = p + 1).
+// Columns j >= n are not skipped: they are zero, so the arithmetic leaves
+// the tile unchanged (sigma^2 = 0, tau = 0, coef = 0) and no value has to be
+// merged across a branch.
+//
+// On return the panel's tails are the scaled reflector tails, td holds the
+// panel's diagonal T block on and above its diagonal (entries below it are
+// never written and must be zero), scl[k] holds the scale of column k, and
+// in MODE != 0 R's rows of the panel hold the panel's columns of the new R.
+// sink: 64 entries a lane writes when its store has no target (every lane
+// stores, so no store sits behind a branch); zero: an entry holding 0.
+//
+// Shared by the one- and two-wave engines, so both produce the same bits.
+template <typename T, int NCP, int MODE, int SG, int NPX, int L, int p, int S1>
+__device__ __forceinline__ void sweep_panel(T (&x)[SG][4][NPX], T* __restrict__ R, T (&td)[16][17],
+                                            T* __restrict__ sink, T* __restrict__ scl, const T* __restrict__ zero,
+                                            const int n_) {
+    typedef Mfma<T> M;
+    constexpr int c0 = 16 * p;
+    constexpr int S0 = (MODE == 0) ? p : 0;
+    const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
+    const int c = c0 + l16;
+    // Column k of the panel's T: T[a][k] = -tau_k sum_{i<k} T[a][i] P[i][k],
+    // T[k][k] = tau_k, with the in-panel Gram entries P[i][k] = v_i^T v_k =
+    // scale_i w_i of column k's step (lanes i < k), in two running sums.
+    // Formed one column late, inside the next column's step, where it
+    // overlaps that column's reduction and Householder scalars.
+    T pw_prev = T(0), tau_prev = T(0);
+    auto tcol = [&](auto kc_) {
+        constexpr int k = decltype(kc_)::value;
+        T tk[2] = {T(0), T(0)};
+        sfor<0, k>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            fmac_bc<i, i == 0>(tk[i & 1], pw_prev, td[l16][i]);
+        });
+        const T t = tk[0] + tk[1];
+        T* dst = (l16 < opaque_s(k)) ? &td[l16][k] : (sink + lane);
+        *dst = -tau_prev * t;
+        td[k][k] = tau_prev;
+    };
+    sfor<0, 16>([&](auto jc) {
+        constexpr int jj = decltype(jc)::value;
+        constexpr int j = c0 + jj;
+        __builtin_amdgcn_sched_barrier(0);
+        // lane conditions of this column, not hoisted out of the sweep
+        const int n = opaque_s(n_);
+        const bool right = c > opaque_s(j);
+        constexpr int hreg = M::row_reg(jj), hl4 = M::row_l4(jj);
+        T alpha, hc;
+        if constexpr (MODE == 0) {
+            const T hv = x[p][hreg][L];
+            alpha = rdlane<16 * hl4 + jj>(hv);
+            hc = sum4((l4 == hl4) ? hv : T(0));
+        } else {
+            // R[j][c] for the trailing columns (zero beyond n), 0 elsewhere
+            alpha = R[rpi<NCP>(j, j)];
+            hc = *(right ? (R + rpi<NCP>(j, 0) + c) : zero);
+        }
+        T xj[SG][4];
+        T acc4[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (MODE == 0) {
+            // column j, broadcast to the lanes of the other columns (tail rows only)
+            sfor<S0, SG>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    T v = bcast16<jj>(x[s][i][L]);
+                    if constexpr (s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
+                    xj[s][i] = v;
+                    acc4[i] = fma(v, x[s][i][L], acc4[i]);
+                }
+            });
+        } else {
+            dot_bc<jj, S1, L, jj == 0>(acc4, x);
+        }
+        if constexpr (jj > 0) tcol(ic_t<jj - 1>{});
+        const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
+        const T sigma2 = bcast16<jj>(g);
+        T beta, tau, scale, rbeta;
+        hh_scalars(alpha, sigma2, beta, tau, scale, rbeta);
+        const bool zt = (sigma2 == T(0));
+        tau = zt ? T(0) : tau;
+        scale = zt ? T(0) : scale;
+        beta = zt ? alpha : beta;
+        const bool trail = right && (c < n);
+        // coef = -tau w scale = w / beta, its factor selected off the critical path
+        const T mcoef = (trail && !zt) ? rbeta : T(0);
+        const T w = fma(scale, g, hc);
+        const T tw = tau * w;
+        const T coef = w * mcoef;
+        if constexpr (MODE != 0) {
+            // R[j][c] -= tau w_c (zero stays zero beyond n); R[j][j] = beta
+            T* dst = right ? (R + rpi<NCP>(j, 0) + c) : (sink + lane);
+            *dst = hc - tw;
+            R[rpi<NCP>(j, j)] = beta;
+        }
+        if constexpr (MODE == 0) {
+            sfor<S0, SG>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[s][i][L] = fma(xj[s][i], coef, x[s][i][L]);
+            });
+            T& hv = x[p][hreg][L];
+            const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);
+            hv = (l4 == hl4) ? nh : hv;
+        } else {
+            upd_bc<jj, S1, L>(x, coef);
+        }
+        // column j keeps its tail unscaled until the panel ends
+        scl[jj] = scale;
+        pw_prev = scl[l16] * w;
+        tau_prev = tau;
+    });
+    tcol(ic_t<15>{});
+    // reflector tails: scale the panel's columns (delayed from the sweep)
+    const T sc_lane = scl[l16];
+    constexpr int SE = (MODE == 0) ? SG : S1;
+    sfor<S0, SE>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if constexpr (MODE == 0 && s == p)
+                x[s][i][L] = (M::orow(l4, i) > l16) ? x[s][i][L] * sc_lane : x[s][i][L];
+            else
+                x[s][i][L] *= sc_lane;
+        }
+    });
+}
 
 // ---- the block factorisation -----------------------------------------------------
 //
@@ -349,124 +506,9 @@ __device__ __forceinline__ void wave_block(T (&x)[SG][4][NP], WSmem<T, NP>& sm, 
         constexpr int S0 = (MODE == 0) ? p : 0;
         constexpr int S1 = (MODE == 2) ? p + 1 : SG;
         const int c = c0 + l16;
-        T sc_lane = T(1), tau_lane = T(0);
-        // in-panel Gram P[c][k] = v_c^T v_k (lanes c < k) and column k of the
-        // panel's T (row l16 per lane group, kept in sm.td[p]):
-        // T[a][k] = -tau_k sum_{i<k} T[a][i] P[i][k], T[k][k] = tau_k (two
-        // running sums over i, so the sum is not one dependent chain).  Formed
-        // one column late, inside the next column's step, where it overlaps
-        // that column's reduction and Householder scalars.
-        T pw_prev = T(0), tau_prev = T(0);
-        auto tcol = [&](auto kc_) {
-            constexpr int k = decltype(kc_)::value;
-            const int l16 = lane_id() & 15;
-            T tk[2] = {T(0), T(0)};
-            sfor<0, k>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                tk[i & 1] = fma(sm.td[p][l16][i], bcast16<i>(pw_prev), tk[i & 1]);
-            });
-            const T t = tk[0] + tk[1];
-            sm.td[p][l16][k] = (l16 < k) ? -tau_prev * t : ((l16 == k) ? tau_prev : T(0));
-        };
-
-        // ------------------------------------------------------ column sweep
-        sfor<0, 16>([&](auto jc) {
-            constexpr int jj = decltype(jc)::value;
-            // Columns j >= n are not skipped: they are zero, so the arithmetic
-            // below leaves the tile unchanged (sigma^2 = 0, tau = 0, coef = 0)
-            // and no value has to be merged across a branch.
-            const int n = opaque_s(n_);
-            const int j = c0 + jj;
-            const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
-            __builtin_amdgcn_sched_barrier(0);
-            const int c = c0 + l16;
-            constexpr int hreg = M::row_reg(jj), hl4 = M::row_l4(jj);
-            T alpha, hc;
-            if constexpr (MODE == 0) {
-                const T hv = x[p][hreg][p];
-                alpha = rdlane<16 * hl4 + jj>(hv);
-                hc = sum4((l4 == hl4) ? hv : T(0));
-            } else {
-                alpha = sm.R[rpi<NCP>(j, j)];
-                T hr = sm.R[rpi<NCP>(j, (c > j) ? c : j)];
-                asm volatile("" : "+v"(hr));  // an unconditional load, not a branch around one
-                hc = (c > j && c < n) ? hr : T(0);
-            }
-            // column j, broadcast to the lanes of the other columns (tail rows only)
-            T xj[SG][4];
-            // four running sums (one per register of a row group), so the
-            // dependent chain is one FMA per row group
-            T acc4[4] = {T(0), T(0), T(0), T(0)};
-            if constexpr (MODE == 0) {
-                sfor<S0, S1>([&](auto sc) {
-                    constexpr int s = decltype(sc)::value;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        T v = bcast16<jj>(x[s][i][p]);
-                        if constexpr (s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
-                        xj[s][i] = v;
-                        acc4[i] = fma(v, x[s][i][p], acc4[i]);
-                    }
-                });
-            } else {
-                dot_bc<jj, S1, p, jj == 0>(acc4, x);
-            }
-            if constexpr (jj > 0) tcol(ic_t<jj - 1>{});
-            const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
-            const T sigma2 = bcast16<jj>(g);
-            T beta, tau, scale;
-            T rbeta;
-            hh_scalars(alpha, sigma2, beta, tau, scale, rbeta);
-            const bool zt = (sigma2 == T(0));
-            tau = zt ? T(0) : tau;
-            scale = zt ? T(0) : scale;
-            beta = zt ? alpha : beta;
-            const bool trail = (c > j) && (c < n);
-            // coef = -tau w scale = w / beta, its factor selected off the critical path
-            const T mcoef = (trail && !zt) ? rbeta : T(0);
-            const T w = fma(scale, g, hc);
-            const T tw = tau * w;
-            const T coef = w * mcoef;
-            if constexpr (MODE != 0) {
-                // every lane stores (the four lanes of a column hold the same
-                // value); lanes left of the diagonal write into the staging tile
-                T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&sm.scr[0][0] + l16);
-                *dst = (c == j) ? beta : hc - tw;
-            }
-            if constexpr (MODE == 0) {
-                sfor<S0, S1>([&](auto sc) {
-                    constexpr int s = decltype(sc)::value;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) x[s][i][p] = fma(xj[s][i], coef, x[s][i][p]);
-                });
-            } else {
-                upd_bc<jj, S1, p>(x, coef);
-            }
-            if constexpr (MODE == 0) {
-                T& hv = x[p][hreg][p];
-                const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);
-                hv = (l4 == hl4) ? nh : hv;
-            }
-            // lane jj keeps its column unscaled until the panel ends (sc_lane)
-            sc_lane = (l16 == jj) ? scale : sc_lane;
-            tau_lane = (l16 == jj) ? tau : tau_lane;
-            pw_prev = sc_lane * w;
-            tau_prev = tau;
-        });
-        tcol(ic_t<15>{});
-
-        // reflector tails: scale the panel's columns (delayed from the sweep)
-        sfor<S0, S1>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if constexpr (MODE == 0 && s == p)
-                    x[s][i][p] = (M::orow(l4, i) > l16) ? x[s][i][p] * sc_lane : x[s][i][p];
-                else
-                    x[s][i][p] *= sc_lane;
-            }
-        });
-        if (WQ && l4 == 0 && c < n) tauout[c] = tau_lane;
+        sweep_panel<T, NCP, MODE, SG, NP, p, p, S1>(x, sm.R, sm.td[p], &sm.scr[0][0], sm.scl, &sm.zero, n_);
+        wave_sync();
+        if (WQ && l4 == 0 && c < n) tauout[c] = sm.td[p][l16][l16];
         done(pc);
         if constexpr (WQ && NP > 1 && p > 0) {
             sfor<0, p>([&](auto ac_) {
@@ -993,6 +1035,10 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
     const int n = (int)g.n;
     const int64_t tri = (int64_t)n * (n + 1) / 2;
     const int64_t nn = (int64_t)n * n;
+    // the sweep writes the diagonal T blocks on and above their diagonals only
+    for (int e = lane_id(); e < NP * 16 * 17; e += 64) (&sm.td[0][0][0])[e] = T(0);
+    if (lane_id() == 0) sm.zero = T(0);
+    wave_sync();
     if constexpr (!CHAIN) {
         // the chain was reduced by another launch: its R is in Rbuf
         r_get<T, NP>(sm, Rbuf + (int64_t)c * rslot<NP>(n));

@@ -42,6 +42,9 @@ struct W2Smem {
     T scr[2][16][17];            // per-wave transposes and the sweep's staging target
     T tdA[kW2Ring][2][16][17];   // wave A's diagonal T blocks (panels 0, 1), one slot per block in flight
     T tdB[kW2Ring][2][16][17];   // wave B's diagonal T blocks (panels 2, 3), one slot per block in flight
+                                 // (entries below the diagonals stay zero)
+    T scl[2][16];                // per-wave scales of the current panel's columns
+    T zero;                      // holds 0
     int ready;                   // blocks whose panels 0 and 1 wave A has published
     int used;                    // blocks whose slot wave B has released (R only)
     int swept;                   // blocks wave B has published (implicit Q kept)
@@ -135,120 +138,15 @@ __device__ __forceinline__ void x_store_tile(const T (&x)[SG][4][2], T* __restri
 // stacked under the on-chip R.
 template <typename T, int SG, int MODE, bool WQ, int P0, int p>
 __device__ __forceinline__ void w2_sweep(T (&x)[SG][4][2], W2Smem<T>& sm, T (&scr)[16][17], T (&td)[16][17],
-                                         const int n_, T* __restrict__ Tout, T* __restrict__ tauout) {
+                                         T (&scl)[16], const int n_, T* __restrict__ Tout, T* __restrict__ tauout) {
     typedef Mfma<T> M;
-    constexpr int NCP = 64;
     constexpr int c0 = 16 * p;
-    constexpr int lt = p - P0;
-    constexpr int S0 = (MODE == 0) ? p : 0;
+    sweep_panel<T, W2Smem<T>::NCP, MODE, SG, 2, p - P0, p, SG>(x, sm.R, td, &scr[0][0], scl, &sm.zero, n_);
     const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
     const int c = c0 + l16;
-    T sc_lane = T(1), tau_lane = T(0);
-    // column k of the panel's T: T[a][k] = -tau_k sum_{i<k} T[a][i] (v_i^T v_k),
-    // formed one column late, inside the next column's step, where it overlaps
-    // that column's reduction and Householder scalars
-    T pw_prev = T(0), tau_prev = T(0);
-    auto tcol = [&](auto kc_) {
-        constexpr int k = decltype(kc_)::value;
-        const int l16 = lane_id() & 15;
-        T tk[2] = {T(0), T(0)};
-        sfor<0, k>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            tk[i & 1] = fma(td[l16][i], bcast16<i>(pw_prev), tk[i & 1]);
-        });
-        const T t = tk[0] + tk[1];
-        td[l16][k] = (l16 < k) ? -tau_prev * t : ((l16 == k) ? tau_prev : T(0));
-    };
-    sfor<0, 16>([&](auto jc) {
-        constexpr int jj = decltype(jc)::value;
-        // columns j >= n are zero: the arithmetic leaves the tile unchanged
-        const int n = opaque_s(n_);
-        const int j = c0 + jj;
-        const int lane = lane_id(), l16 = lane & 15, l4 = lane >> 4;
-        __builtin_amdgcn_sched_barrier(0);
-        const int c = c0 + l16;
-        constexpr int hreg = M::row_reg(jj), hl4 = M::row_l4(jj);
-        T alpha, hc;
-        if constexpr (MODE == 0) {
-            const T hv = x[p][hreg][lt];
-            alpha = rdlane<16 * hl4 + jj>(hv);
-            hc = sum4((l4 == hl4) ? hv : T(0));
-        } else {
-            alpha = sm.R[rpi<NCP>(j, j)];
-            T hr = sm.R[rpi<NCP>(j, (c > j) ? c : j)];
-            asm volatile("" : "+v"(hr));  // an unconditional load, not a branch around one
-            hc = (c > j && c < n) ? hr : T(0);
-        }
-        T xj[SG][4];
-        T acc4[4] = {T(0), T(0), T(0), T(0)};
-        if constexpr (MODE == 0) {
-            sfor<S0, SG>([&](auto sc) {
-                constexpr int s = decltype(sc)::value;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    T v = bcast16<jj>(x[s][i][lt]);
-                    if constexpr (s == p) v = (M::orow(l4, i) > jj) ? v : T(0);
-                    xj[s][i] = v;
-                    acc4[i] = fma(v, x[s][i][lt], acc4[i]);
-                }
-            });
-        } else {
-            dot_bc<jj, SG, lt, jj == 0>(acc4, x);
-        }
-        if constexpr (jj > 0) tcol(ic_t<jj - 1>{});
-        const T g = sum4((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
-        const T sigma2 = bcast16<jj>(g);
-        T beta, tau, scale;
-        T rbeta;
-        hh_scalars(alpha, sigma2, beta, tau, scale, rbeta);
-        const bool zt = (sigma2 == T(0));
-        tau = zt ? T(0) : tau;
-        scale = zt ? T(0) : scale;
-        beta = zt ? alpha : beta;
-        const bool trail = (c > j) && (c < n);
-        // coef = -tau w scale = w / beta, its factor selected off the critical path
-        const T mcoef = (trail && !zt) ? rbeta : T(0);
-        const T w = fma(scale, g, hc);
-        const T tw = tau * w;
-        const T coef = w * mcoef;
-        if constexpr (MODE != 0) {
-            // every lane stores; lanes left of the diagonal write into the staging tile
-            T* dst = (c >= j) ? (sm.R + rpi<NCP>(j, (c > j) ? c : j)) : (&scr[0][0] + l16);
-            *dst = (c == j) ? beta : hc - tw;
-        }
-        if constexpr (MODE == 0) {
-            sfor<S0, SG>([&](auto sc) {
-                constexpr int s = decltype(sc)::value;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) x[s][i][lt] = fma(xj[s][i], coef, x[s][i][lt]);
-            });
-        } else {
-            upd_bc<jj, SG, lt>(x, coef);
-        }
-        if constexpr (MODE == 0) {
-            T& hv = x[p][hreg][lt];
-            const T nh = (l16 == jj) ? beta : (trail ? hv - tw : hv);
-            hv = (l4 == hl4) ? nh : hv;
-        }
-        sc_lane = (l16 == jj) ? scale : sc_lane;
-        tau_lane = (l16 == jj) ? tau : tau_lane;
-        pw_prev = sc_lane * w;
-        tau_prev = tau;
-    });
-    tcol(ic_t<15>{});
-    sfor<S0, SG>([&](auto sc) {
-        constexpr int s = decltype(sc)::value;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if constexpr (MODE == 0 && s == p)
-                x[s][i][lt] = (M::orow(l4, i) > l16) ? x[s][i][lt] * sc_lane : x[s][i][lt];
-            else
-                x[s][i][lt] *= sc_lane;
-        }
-    });
     const int n = opaque_s(n_);
-    if (WQ && l4 == 0 && c < n) tauout[c] = tau_lane;
     wave_sync();
+    if (WQ && l4 == 0 && c < n) tauout[c] = td[l16][l16];
     if constexpr (WQ) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -521,7 +419,12 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     for (int e = threadIdx.x; e < W2Smem<T>::RP; e += 128) sm.R[e] = T(0);
+    for (int e = threadIdx.x; e < kW2Ring * 2 * 16 * 17; e += 128) {
+        (&sm.tdA[0][0][0][0])[e] = T(0);
+        (&sm.tdB[0][0][0][0])[e] = T(0);
+    }
     if (threadIdx.x == 0) {
+        sm.zero = T(0);
         sm.ready = 0;
         sm.used = 0;
         sm.swept = 0;
@@ -549,7 +452,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
             if (!WQ && b >= kW2Ring) lds_wait_ge(&sm.used, b - kW2Ring + 1);
             auto blockA = [&](auto mc) {
                 constexpr int MODE = decltype(mc)::value;
-                w2_sweep<T, SG, MODE, WQ, 0, 0>(x, sm, sm.scr[0], sm.tdA[slot][0], n, Tout, tauout);
+                w2_sweep<T, SG, MODE, WQ, 0, 0>(x, sm, sm.scr[0], sm.tdA[slot][0], sm.scl[0], n, Tout, tauout);
                 x_store_tile<T, SG, 0, 0>(x, A, lda, r0, rows, n);
                 {
                     T v0[SG][4];
@@ -561,7 +464,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                 }
                 if constexpr (MODE == 0) w2_rows_to_r<T, SG, 0, 0>(x, sm, n);
                 if (16 < n) {
-                    w2_sweep<T, SG, MODE, WQ, 0, 1>(x, sm, sm.scr[0], sm.tdA[slot][1], n, Tout, tauout);
+                    w2_sweep<T, SG, MODE, WQ, 0, 1>(x, sm, sm.scr[0], sm.tdA[slot][1], sm.scl[0], n, Tout, tauout);
                     if constexpr (MODE == 0) w2_rows_to_r<T, SG, 0, 1>(x, sm, n);
                 } else {
                     // panel 1 lies beyond n: its diagonal T block is zero
@@ -625,7 +528,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                 if constexpr (!WQ) lds_store_rel(&sm.used, b + 1);
                 // panels 2 and 3 (columns beyond n are zero: no skip needed
                 // past panel 2, which n > 32 reaches)
-                w2_sweep<T, SG, MODE, WQ, 2, 2>(x, sm, sm.scr[1], sm.tdB[slot][0], n, Tout, tauout);
+                w2_sweep<T, SG, MODE, WQ, 2, 2>(x, sm, sm.scr[1], sm.tdB[slot][0], sm.scl[1], n, Tout, tauout);
                 x_store_tile<T, SG, 2, 0>(x, A, lda, r0, rows, n);
                 {
                     T v2[SG][4];
@@ -637,7 +540,7 @@ __device__ __forceinline__ void w2_chain(W2Smem<T>& sm, const Geom& g, int ch, T
                 }
                 if constexpr (MODE == 0) w2_rows_to_r<T, SG, 2, 2>(x, sm, n);
                 if (48 < n) {
-                    w2_sweep<T, SG, MODE, WQ, 2, 3>(x, sm, sm.scr[1], sm.tdB[slot][1], n, Tout, tauout);
+                    w2_sweep<T, SG, MODE, WQ, 2, 3>(x, sm, sm.scr[1], sm.tdB[slot][1], sm.scl[1], n, Tout, tauout);
                     if constexpr (MODE == 0) w2_rows_to_r<T, SG, 2, 3>(x, sm, n);
                 } else {
                     for (int e = lane; e < 16 * 17; e += 64) (&sm.tdB[slot][1][0][0])[e] = T(0);
