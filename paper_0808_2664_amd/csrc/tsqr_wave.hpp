@@ -947,7 +947,7 @@ __device__ __forceinline__ int producer_level(int W, int l, int idx) {
 template <typename T, int NP, bool WQ>
 __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, int c, T* __restrict__ Rbuf,
                                                T* __restrict__ Ynode, T* __restrict__ Tnode,
-                                               T* __restrict__ tau_node, const TreeArgs& ta) {
+                                               T* __restrict__ tau_node, const TreeArgs& ta, bool in_rbuf) {
     constexpr int NCP = 16 * NP;
     constexpr int RP = WSmem<T, NP>::RP;
     const int n = (int)g.n;
@@ -958,9 +958,12 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
     const int64_t nn = (int64_t)n * n;
     int* prog = ta.cnt;
     const int lane = lane_id();
-    // publish the chain's R (all panels at once)
-    r_pub<T, NP>(sm, Rbuf + (int64_t)c * rs);
-    pub_wait();
+    // publish the chain's R (all panels at once); a chain reduced by an
+    // earlier launch left it in its slot already
+    if (!in_rbuf) {
+        r_pub<T, NP>(sm, Rbuf + (int64_t)c * rs);
+        pub_wait();
+    }
     if (lane == 0) pub_flag(prog + c, npl);
     if (c % g.cpm == 0) return;  // a member's first chain performs no node
     const int lev = __builtin_ctz((unsigned)c) + 1;
@@ -969,7 +972,7 @@ __device__ __forceinline__ void wave_tree_pipe(WSmem<T, NP>& sm, const Geom& g, 
     const bool own_b = lb == 0;  // the second child is this wave's own chain
     T x[NP][4][NP];
     if (own_b) {
-        tile_of_packed<T, NP>(x, sm.R, n);
+        tile_of_packed<T, NP>(x, in_rbuf ? (const T*)(Rbuf + (int64_t)c * rs) : (const T*)sm.R, n);
         wave_sync();
     }
     const T* Ra = Rbuf + (int64_t)i0 * rs;
@@ -1040,8 +1043,9 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
     if (lane_id() == 0) sm.zero = T(0);
     wave_sync();
     if constexpr (!CHAIN) {
-        // the chain was reduced by another launch: its R is in Rbuf
-        r_get<T, NP>(sm, Rbuf + (int64_t)c * rslot<NP>(n));
+        // the chain was reduced by another launch: its R is in Rbuf, where
+        // the pipelined tree reads it
+        if (!PIPE || g.levels == 0) r_get<T, NP>(sm, Rbuf + (int64_t)c * rslot<NP>(n));
     } else {
         // R starts at zero, so its entries beyond column n stay zero
         for (int e = lane_id(); e < (int)(sizeof(sm.R) / sizeof(T)); e += 64) sm.R[e] = T(0);
@@ -1082,7 +1086,7 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         return;
     }
     if constexpr (PIPE) {
-        wave_tree_pipe<T, NP, WQ>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta);
+        wave_tree_pipe<T, NP, WQ>(sm, g, c, Rbuf, Ynode, Tnode, tau_node, ta, !CHAIN);
         return;
     }
     const int64_t rs = rslot<NP>(n);
@@ -1094,8 +1098,11 @@ __device__ __forceinline__ void wave_tsqr(WSmem<T, NP>& sm, const Geom& g, int c
         int nch = (int)((g.W - i0 + stride - 1) / stride);
         if (nch > g.arity) nch = g.arity;
         if (nch <= 1) continue;  // unpaired: carried up unchanged
-        r_pub<T, NP>(sm, Rbuf + (int64_t)cur * rs);
-        pub_wait();
+        // (a chain reduced by an earlier launch left its R in its slot already)
+        if (CHAIN || lev > 1) {
+            r_pub<T, NP>(sm, Rbuf + (int64_t)cur * rs);
+            pub_wait();
+        }
         int old = 0;
         if ((threadIdx.x & 63) == 0) old = atomicAdd(ta.cnt + (int64_t)(lev - 1) * g.W + i0, 1);
         old = __builtin_amdgcn_readfirstlane(old);
