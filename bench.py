@@ -36,9 +36,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector / matrix, published
 METRIC = "TSQR/CAQR GFLOP/s + HBM GB/s vs roofline; batched & fwd+bwd vs plain"
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_wave_tsqr_2p20x64_f64.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_factor_2p20x64_f64.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_0808_2664_amd", "csrc", f)
-              for f in ("tsqr_factor.hip", "tsqr_wave.hpp", "tsqr_common.hpp")]
+              for f in ("tsqr_factor.hip", "tsqr_factor_kernel.hpp", "tsqr_wave.hpp", "tsqr_wave2.hpp",
+                        "tsqr_common.hpp")]
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector / matrix, published
 
 
@@ -82,9 +83,10 @@ def src_hash(paths):
 
 
 def traffic_from_profile(m, n):
-    """HBM bytes per launch of the chain factor kernel from committed
-    rocprofv3 counters (FETCH_SIZE / WRITE_SIZE), scaled by a copy kernel of
-    known size; null if absent or taken on another version of the kernel."""
+    """HBM bytes per factor call (the chain kernel and the tree launch) from
+    committed rocprofv3 counters (FETCH_SIZE / WRITE_SIZE), scaled by a copy
+    kernel of known size; null if absent or taken on another version of the
+    kernels."""
     try:
         with open(PMC_FILE) as f:
             d = json.load(f)
@@ -241,7 +243,7 @@ def main():
     traffic = traffic_from_profile(m, n)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_wave_tsqr (chains and tree of one TSQR, one launch)",
+            "kernel": "TSQR factor: k_chain2 (two-wave chains) + k_wave_tsqr (pipelined tree), two launches",
             "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": by[0]}
     cpu = None
     if a.cpu_rows > 0:
