@@ -355,13 +355,41 @@ constexpr int W_TRI = 64 * 65 / 2;
 template <typename C>
 struct WideSmem {
     C Y[64][WY_PITCH];
-    C T[W_TRI];
+    C T[W_TRI + 1];  // T (or -T), packed column by column; T[W_TRI] = 0 where used
 };
 
-// Entry (i, j), i <= j, of the block's T (packed column by column).
+// Global access at a wave-uniform base plus a 32-bit per-lane byte offset:
+// the form the scalar-base vector memory instructions take, so no per-lane
+// 64-bit address arithmetic is spent on it.
+// (The offset passes through an empty asm so the optimiser does not fold it
+// into a 64-bit per-lane address computed once outside the block loop.)
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return *(const T*)((const char*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
+    asm volatile("" : "+v"(off));
+    *(T*)((char*)base + off) = v;
+}
+
+// Entry (i, j), i <= j, of a block's T staged as is (packed column by column).
 template <typename C>
 __device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
     return sm.T[j * (j + 1) / 2 + i];
+}
+
+// Index in WideSmem::T of the A operand (row 16a + orow(l4, kc), column
+// 16b + l16 of the 16 x 16 block (a, b) of T, or of T^T when TR) of lane
+// (l16, l4): entries below T's diagonal index the zero slot.  The same for
+// every block, so computed once per workgroup.
+template <typename C>
+__device__ __forceinline__ int wide_toff(int a, int b, int kc, int l4, int l16, bool tr) {
+    typedef Mfma<C> M;
+    const int r = 16 * a + M::orow(l4, kc), c = 16 * b + l16;
+    const int i = tr ? c : r, j = tr ? r : c;
+    return (i <= j) ? j * (j + 1) / 2 + i : W_TRI;
 }
 
 // TW waves per workgroup (2 or 4), so 16 TW columns of B per workgroup.
@@ -385,6 +413,17 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
     const int nb = chain_nblocks(g, chain);
     const int64_t blk0 = chain_blk0(g, chain);
     auto blk = [&](int bi) { return (MODE == MODE_QT) ? bi : nb - 1 - bi; };
+    // Full blocks of a workgroup whose columns are all inside B take the fast
+    // accesses: a uniform row base and a 32-bit lane offset (rows
+    // 16r + orow(l4, i) of a block: base row 16r, offset boff[i]).
+    const bool colall = (int64_t)grp * (16 * TW) + 16 * TW <= k &&
+                        (int64_t)(16 * ldb + k) * (int64_t)sizeof(S) < ((int64_t)1 << 31) &&
+                        (int64_t)(64 * ldy) * (int64_t)sizeof(S) < ((int64_t)1 << 31);
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    uint32_t boff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) boff[i] = (uint32_t)(((int64_t)M::orow(l4, i) * ldb + col) * (int64_t)sizeof(S));
+    const uint32_t loff = (uint32_t)(lane * (int)sizeof(S)), toff0 = (uint32_t)(tid * (int)sizeof(S));
     // row of register kk = 4r + i of the accumulator layout
     auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
     // staging of one block's Y (rows TW t + wv, column lane) and packed T
@@ -393,16 +432,25 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         const int b = blk(bi);
         const int64_t r0 = start + (int64_t)b * 64;
         const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+        if (rows == 64 && colall) {
 #pragma unroll
-        for (int t = 0; t < YS; ++t) {
-            const int r = TW * t + wv;
-            ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : S(0);
+            for (int t = 0; t < YS; ++t) ys[t] = ld_off(Y + (r0 + TW * t + wvu) * ldy, loff);
+        } else {
+#pragma unroll
+            for (int t = 0; t < YS; ++t) {
+                const int r = TW * t + wv;
+                ys[t] = (r < rows) ? Y[(r0 + r) * ldy + lane] : S(0);
+            }
         }
         const S* Tb = T_blk + (blk0 + b) * W_TRI;
 #pragma unroll
         for (int t = 0; t < TSN; ++t) {
-            const int e = tid + NT * t;
-            ts[t] = (e < W_TRI) ? Tb[e] : S(0);
+            if ((t + 1) * NT <= W_TRI) {
+                ts[t] = ld_off(Tb + NT * t, toff0);
+            } else {
+                const int e = tid + NT * t;
+                ts[t] = (e < W_TRI) ? Tb[e] : S(0);
+            }
         }
     };
     auto stage_store = [&](int bi) {
@@ -415,7 +463,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
         for (int t = 0; t < TSN; ++t) {
             const int e = tid + NT * t;
-            if (e < W_TRI) sm.T[e] = (C)ts[t];
+            if (e < W_TRI) sm.T[e] = -(C)ts[t];
         }
     };
     S xn[16];
@@ -424,6 +472,13 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         const int64_t r0 = start + (int64_t)b * 64;
         const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
         const bool zero = (MODE == MODE_FORMQ) || (MODE != MODE_QT && b == 0);  // zero rows / the slab
+        if (!zero && rows == 64 && colall) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xn[4 * r + i] = ld_off(B + (r0 + 16 * r) * ldb, boff[i]);
+            return;
+        }
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             const int r = xrow(kk);
@@ -437,8 +492,23 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * p + M::orow(l4, i);
-            sl[p][i] = (MODE != MODE_QT && colok) ? B[(start + r) * ldb + col] : S(0);
+            if (MODE == MODE_QT) sl[p][i] = S(0);
+            else if (colall) sl[p][i] = ld_off(B + (start + 16 * p) * ldb, boff[i]);
+            else sl[p][i] = colok ? B[(start + r) * ldb + col] : S(0);
         }
+    // A operands of W' = T^T W (Q^T) or T W (Q): LDS indices per (p, q, kc)
+    int toff[4][4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc)
+                toff[p][q][kc] = (MODE == MODE_QT) ? wide_toff<C>(q, p, kc, l4, l16, false)
+                                                   : wide_toff<C>(q, p, kc, l4, l16, true);
+        }
+    if (tid == 0) sm.T[W_TRI] = C(0);
     S x[16];
     stage_load(0);
     x_load(0);
@@ -488,13 +558,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             for (int q = 0; q < 4; ++q) {
                 if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) {
-                    const int ti = 16 * q + M::orow(l4, kc);
-                    const int tj = 16 * p + l16;
-                    const C a = (MODE == MODE_QT) ? ((ti <= tj) ? wide_t(sm, ti, tj) : C(0))
-                                                  : ((tj <= ti) ? wide_t(sm, tj, ti) : C(0));
-                    nw[p] = M::mma(-a, w[q][kc], nw[p]);
-                }
+                for (int kc = 0; kc < 4; ++kc) nw[p] = M::mma(sm.T[toff[p][q][kc]], w[q][kc], nw[p]);
             }
         }
         // S -= W'
@@ -526,10 +590,17 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
         } else {
             const int64_t r0 = start + (int64_t)b * 64;
             const int rows = (int)((end - r0) < 64 ? (end - r0) : 64);
+            if (rows == 64 && colall) {
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int r = xrow(kk);
-                if (r < rows && colok) B[(r0 + r) * ldb + col] = x[kk];
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) st_off(B + (r0 + 16 * r) * ldb, boff[i], x[4 * r + i]);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int r = xrow(kk);
+                    if (r < rows && colok) B[(r0 + r) * ldb + col] = x[kk];
+                }
             }
         }
         if (more) {
@@ -540,7 +611,12 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             for (int kk = 0; kk < 16; ++kk) x[kk] = xn[kk];
         }
     }
-    if (MODE == MODE_QT && colok) {
+    if (MODE == MODE_QT && colall) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) st_off(B + (start + 16 * p) * ldb, boff[i], sl[p][i]);
+    } else if (MODE == MODE_QT && colok) {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
