@@ -355,7 +355,7 @@ constexpr int W_TRI = 64 * 65 / 2;
 template <typename C>
 struct WideSmem {
     C Y[64][WY_PITCH];
-    C T[W_TRI + 1];  // T (or -T), packed column by column; T[W_TRI] = 0 where used
+    C T[W_TRI];
 };
 
 // Global access at a wave-uniform base plus a 32-bit per-lane byte offset:
@@ -380,27 +380,26 @@ __device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
     return sm.T[j * (j + 1) / 2 + i];
 }
 
-// Index in WideSmem::T of the A operand (row 16a + orow(l4, kc), column
-// 16b + l16 of the 16 x 16 block (a, b) of T, or of T^T when TR) of lane
-// (l16, l4): entries below T's diagonal index the zero slot.  The same for
-// every block, so computed once per workgroup.
+// The chain kernel's LDS: the block's Y, and -T as a full 64 x 64 matrix
+// (zero below the diagonal), so an A operand of W' = T^T W or T W is one
+// read at a lane offset fixed for the kernel, with no triangle test.
+constexpr int WT_PITCH = 65;
 template <typename C>
-__device__ __forceinline__ int wide_toff(int a, int b, int kc, int l4, int l16, bool tr) {
-    typedef Mfma<C> M;
-    const int r = 16 * a + M::orow(l4, kc), c = 16 * b + l16;
-    const int i = tr ? c : r, j = tr ? r : c;
-    return (i <= j) ? j * (j + 1) / 2 + i : W_TRI;
-}
+struct WideSmemF {
+    C Y[64][WY_PITCH];
+    C Tn[64][WT_PITCH];
+};
 
-// TW waves per workgroup (2 or 4), so 16 TW columns of B per workgroup.
+// TW waves per workgroup (2 or 4), so 16 TW columns of B per workgroup;
+// with four waves two workgroups share a CU (two waves per SIMD).
 template <typename S, typename C, int MODE, int TW>
-__global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW == 4) ? 2 : 1) void k_chain_apply_w(
+__global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
     Geom g, const S* __restrict__ Y, int64_t ldy, const S* __restrict__ T_blk, S* __restrict__ B, int64_t ldb, int64_t k,
     int ngroups) {
     constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
     typedef Mfma<C> M;
     typedef typename M::acc acc_t;
-    __shared__ WideSmem<C> sm;
+    __shared__ WideSmemF<C> sm;
     const int gid = blockIdx.x;
     const int x8 = gid & 7, yq = gid >> 3;
     const int chain = (yq / ngroups) * 8 + x8;
@@ -453,6 +452,13 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             }
         }
     };
+    // where packed entry e of T (column j, row i) goes in Tn
+    auto tdst = [](int e) {
+        int j = (int)((__builtin_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        j -= (j * (j + 1) / 2 > e) ? 1 : 0;
+        j += ((j + 1) * (j + 2) / 2 <= e) ? 1 : 0;
+        return (e - j * (j + 1) / 2) * WT_PITCH + j;
+    };
     auto stage_store = [&](int bi) {
         const bool top = blk(bi) == 0;
 #pragma unroll
@@ -463,7 +469,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
         for (int t = 0; t < TSN; ++t) {
             const int e = tid + NT * t;
-            if (e < W_TRI) sm.T[e] = -(C)ts[t];
+            if (e < W_TRI) (&sm.Tn[0][0])[tdst(e)] = -(C)ts[t];
         }
     };
     S xn[16];
@@ -496,19 +502,11 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             else if (colall) sl[p][i] = ld_off(B + (start + 16 * p) * ldb, boff[i]);
             else sl[p][i] = colok ? B[(start + r) * ldb + col] : S(0);
         }
-    // A operands of W' = T^T W (Q^T) or T W (Q): LDS indices per (p, q, kc)
-    int toff[4][4][4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc)
-                toff[p][q][kc] = (MODE == MODE_QT) ? wide_toff<C>(q, p, kc, l4, l16, false)
-                                                   : wide_toff<C>(q, p, kc, l4, l16, true);
-        }
-    if (tid == 0) sm.T[W_TRI] = C(0);
+    // Tn below the diagonal is zero for every block (staging writes the rest)
+    for (int e = tid; e < 64 * WT_PITCH; e += NT) {
+        const int i = e / WT_PITCH, j = e - i * WT_PITCH;
+        if (i > j) (&sm.Tn[0][0])[e] = C(0);
+    }
     S x[16];
     stage_load(0);
     x_load(0);
@@ -527,20 +525,14 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
                 for (int i = 0; i < 4; ++i) x[4 * p + i] = sl[p][i];
         }
-        // the next block's loads fly during the whole block where the
-        // register file has room for them (one wave per SIMD, four waves),
-        // else during X -= Y W' only
-        constexpr bool early = TW == 4 && (sizeof(C) == 8 || MODE == MODE_QT);
-        if (early && more) {
-            stage_load(bi + 1);
-            x_load(bi + 1);
-        }
         // W = V^T [S; X]
         acc_t w[4];
         const bool xzero = (MODE == MODE_FORMQ) && !top;
         C xc[16];
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) xc[kk] = (C)x[kk];
+        // (scheduling fences between the products' groups keep the operand
+        // reads from LDS from all being hoisted ahead: two waves share a SIMD)
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             w[p] = top ? acc_t{0, 0, 0, 0} : vcvt<acc_t>(sl[p]);
@@ -548,6 +540,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
 #pragma unroll
                 for (int kk = 0; kk < 16; ++kk) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], xc[kk], w[p]);
             }
+            if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
         }
         // W' = T^T W (Q^T) or T W (Q); kept negated
         acc_t nw[4];
@@ -558,17 +551,18 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
             for (int q = 0; q < 4; ++q) {
                 if (MODE == MODE_QT ? (q > p) : (q < p)) continue;
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) nw[p] = M::mma(sm.T[toff[p][q][kc]], w[q][kc], nw[p]);
+                for (int kc = 0; kc < 4; ++kc) {
+                    const C a = (MODE == MODE_QT) ? sm.Tn[16 * q + M::orow(l4, kc)][16 * p + l16]
+                                                  : sm.Tn[16 * p + l16][16 * q + M::orow(l4, kc)];
+                    nw[p] = M::mma(a, w[q][kc], nw[p]);
+                }
             }
+            if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
         }
         // S -= W'
         if (!top) {
 #pragma unroll
             for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
-        }
-        if (!early && more) {
-            stage_load(bi + 1);
-            x_load(bi + 1);
         }
         // X -= Y W'
 #pragma unroll
@@ -580,6 +574,7 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
                 for (int kc = 0; kc < 4; ++kc) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
 #pragma unroll
             for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? x[4 * r + i] + (S)u[i] : (S)u[i];
+            if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
         }
         if (MODE == MODE_QT && top) {
             // the chain's first block becomes the slab
@@ -603,8 +598,17 @@ __global__ __launch_bounds__(64 * TW, (sizeof(C) == 4 && MODE != MODE_QT && TW =
                 }
             }
         }
+        // the next block's loads (after this block's stores, whose registers
+        // they reuse), in flight while the other workgroup on the CU computes;
+        // with four waves the next Y and T come in after the barrier (no
+        // registers to hold them through the block)
+        if (more) {
+            if constexpr (TW != 4) stage_load(bi + 1);
+            x_load(bi + 1);
+        }
         if (more) {
             __syncthreads();  // every wave is done with this block's Y and T
+            if constexpr (TW == 4) stage_load(bi + 1);
             stage_store(bi + 1);
             __syncthreads();
 #pragma unroll
