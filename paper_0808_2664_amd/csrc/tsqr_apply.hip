@@ -343,12 +343,14 @@ __global__ __launch_bounds__(256, 2) void k_chain_apply64(Geom g, const S* __res
 // in the MFMA accumulator layout (x[4r + i] = row 16r + orow(l4, i)); the
 // V^T X product sums over the rows in that same order, so x is also its B
 // operand, and W and W' are used as B operands exactly as the products leave
-// them: no transposes.  The block's Y (64 x 64, row pitch 66) and packed T
-// are staged once per workgroup in LDS (in the compute type) and read as A
-// operands; the next block's Y, T and rows of B are loaded into registers
-// (in the storage type) while the current block is processed.
-// One wave per SIMD (two for the FP32 Q and explicit-Q forms): the register
-// file lets the LDS operand reads run far ahead of the MFMAs that use them.
+// them: no transposes.  The block's Y (64 x 64, row pitch 66) and -T (a
+// full 64 x 64 matrix, zero below the diagonal) are staged once per
+// workgroup in LDS (in the compute type) and read as A operands.
+// Four waves: two workgroups per CU (two waves per SIMD, 256 registers), the
+// next block's rows of B loaded after the block's stores and its Y and T
+// after the block's barrier, while the other workgroup computes.  Two waves
+// (32 columns): one wave per SIMD, the next block's Y, T and rows of B
+// loaded into registers (in the storage type) during X -= Y W'.
 constexpr int WY_PITCH = 66;
 constexpr int W_TRI = 64 * 65 / 2;
 
@@ -564,6 +566,11 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
 #pragma unroll
             for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
         }
+        // two waves (one per SIMD): the next block's loads fly during X -= Y W'
+        if (TW != 4 && more) {
+            stage_load(bi + 1);
+            x_load(bi + 1);
+        }
         // X -= Y W'
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -598,14 +605,11 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
                 }
             }
         }
-        // the next block's loads (after this block's stores, whose registers
-        // they reuse), in flight while the other workgroup on the CU computes;
-        // with four waves the next Y and T come in after the barrier (no
-        // registers to hold them through the block)
-        if (more) {
-            if constexpr (TW != 4) stage_load(bi + 1);
-            x_load(bi + 1);
-        }
+        // four waves (two per SIMD): the next block's rows are loaded after
+        // this block's stores, whose registers they reuse, and its Y and T
+        // after the barrier (no registers to hold them through the block);
+        // the other workgroup on the CU computes meanwhile
+        if (TW == 4 && more) x_load(bi + 1);
         if (more) {
             __syncthreads();  // every wave is done with this block's Y and T
             if constexpr (TW == 4) stage_load(bi + 1);
