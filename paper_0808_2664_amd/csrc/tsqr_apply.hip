@@ -376,6 +376,27 @@ __device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
     *(T*)((char*)base + off) = v;
 }
 
+template <typename T>
+__device__ __forceinline__ T pub_load_off(const T* base, uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return pub_load((const T*)((const char*)base + off));
+}
+template <typename T>
+__device__ __forceinline__ void pub_store_off(T* base, uint32_t off, T v) {
+    asm volatile("" : "+v"(off));
+    pub_store((T*)((char*)base + off), v);
+}
+
+// Row pitch of the full -T staged in LDS (WideSmemF below).
+constexpr int WT_PITCH = 65;
+// Index in WideSmemF::Tn of entry e of a T packed column by column.
+__device__ __forceinline__ int wide_tdst(int e) {
+    int j = (int)((__builtin_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    j -= (j * (j + 1) / 2 > e) ? 1 : 0;
+    j += ((j + 1) * (j + 2) / 2 <= e) ? 1 : 0;
+    return (e - j * (j + 1) / 2) * WT_PITCH + j;
+}
+
 // Entry (i, j), i <= j, of a block's T staged as is (packed column by column).
 template <typename C>
 __device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
@@ -385,7 +406,6 @@ __device__ __forceinline__ C wide_t(const WideSmem<C>& sm, int i, int j) {
 // The chain kernel's LDS: the block's Y, and -T as a full 64 x 64 matrix
 // (zero below the diagonal), so an A operand of W' = T^T W or T W is one
 // read at a lane offset fixed for the kernel, with no triangle test.
-constexpr int WT_PITCH = 65;
 template <typename C>
 struct WideSmemF {
     C Y[64][WY_PITCH];
@@ -454,12 +474,16 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
             }
         }
     };
-    // where packed entry e of T (column j, row i) goes in Tn
-    auto tdst = [](int e) {
-        int j = (int)((__builtin_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-        j -= (j * (j + 1) / 2 > e) ? 1 : 0;
-        j += ((j + 1) * (j + 2) / 2 <= e) ? 1 : 0;
-        return (e - j * (j + 1) / 2) * WT_PITCH + j;
+    // where packed entry e = tid + NT t of T goes in Tn: kept in registers
+    // with two waves (one per SIMD), recomputed with four (256 registers)
+    int tdp[TW == 4 ? 1 : TSN];
+    if constexpr (TW != 4) {
+#pragma unroll
+        for (int t = 0; t < TSN; ++t) tdp[t] = wide_tdst(tid + NT * t);
+    }
+    auto tdst = [&](int t) {
+        if constexpr (TW == 4) return wide_tdst(tid + NT * t);
+        else return tdp[t];
     };
     auto stage_store = [&](int bi) {
         const bool top = blk(bi) == 0;
@@ -471,7 +495,7 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
 #pragma unroll
         for (int t = 0; t < TSN; ++t) {
             const int e = tid + NT * t;
-            if (e < W_TRI) (&sm.Tn[0][0])[tdst(e)] = -(C)ts[t];
+            if (e < W_TRI) (&sm.Tn[0][0])[tdst(t)] = -(C)ts[t];
         }
     };
     S xn[16];
@@ -632,7 +656,9 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
     }
 }
 
-// Tree levels of Q^T for n = 64 with 64 columns per workgroup, as
+// Tree levels of Q^T for n = 64, two waves (32 columns) per workgroup: the
+// form of k_qt_tree_w below with T packed in LDS and one workgroup's steps
+// in registers (one wave per SIMD), as
 // k_qt_tree64 (level-1 node per workgroup, then the last arrival performs a
 // node), each wave owning a 16-column tile over all 64 slab rows as in
 // k_chain_apply_w; a step's Y_node and T_node are staged in LDS.
@@ -641,7 +667,7 @@ __global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_chain_apply_w(
 // the block diagonal are exact zeros and their products are skipped (here
 // and in k_node_apply_w); the results are the same bits.
 template <typename S, typename C, int TW>
-__global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
+__global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w2(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
                                                           int64_t k, const S* __restrict__ Ynode,
                                                           const S* __restrict__ Tnode, int* __restrict__ cnt) {
     constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
@@ -749,6 +775,157 @@ __global__ __launch_bounds__(64 * TW, 1) void k_qt_tree_w(Geom g, int ngroups, S
             }
         }
         if (colok) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pub_store(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col, (S)sl[p][i]);
+        }
+        cur = i0;
+    }
+}
+
+// Tree levels of Q^T for n = 64 with 64 columns per workgroup, as
+// k_qt_tree64 (level-1 node per workgroup, then the last arrival performs a
+// node), each wave owning a 16-column tile over all 64 slab rows as in
+// k_chain_apply_w; a step's Y_node and T_node are staged in LDS.
+// A node's reflector tails sit in the positions of a child's upper triangle
+// (Sec. 2.1: the stacked-triangle QR), so the 16 x 16 tiles of Y_node below
+// the block diagonal are exact zeros and their products are skipped (here
+// and in k_node_apply_w); the results are the same bits.
+template <typename S, typename C, int TW>
+__global__ __launch_bounds__(64 * TW, TW == 4 ? 2 : 1) void k_qt_tree_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
+                                                          int64_t k, const S* __restrict__ Ynode,
+                                                          const S* __restrict__ Tnode, int* __restrict__ cnt) {
+    constexpr int NT = 64 * TW, YS = 64 / TW;
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    __shared__ WideSmemF<C> sm;
+    __shared__ int s_old;
+    const int node = blockIdx.x / ngroups;
+    const int grp = blockIdx.x - node * ngroups;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)grp * (16 * TW) + 16 * wv + l16;
+    const bool colok = col < k;
+    auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
+    int cur = node * g.arity;
+    if (cur >= g.W) return;
+    // as in k_chain_apply_w: uniform row bases and 32-bit lane offsets when
+    // every column of the workgroup lies inside B
+    const bool colall = (int64_t)grp * (16 * TW) + 16 * TW <= k &&
+                        (int64_t)(16 * ldb + k) * (int64_t)sizeof(S) < ((int64_t)1 << 31);
+    uint32_t boff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) boff[i] = (uint32_t)(((int64_t)M::orow(l4, i) * ldb + col) * (int64_t)sizeof(S));
+    // -T is staged over the whole 64 x 64 square (entry i, j of thread
+    // tid + NT u, i = e / 64, j = e % 64), zeros below the diagonal included:
+    // a workgroup applies few steps, so no separate clearing pass
+    constexpr int TSF = 4096 / NT;
+    bool staged = false;  // LDS holds a previous step's operands
+    for (int lev = 1; lev <= g.levels; ++lev) {
+        const int64_t stride = ipow(g.arity, lev - 1);
+        const int64_t span = stride * g.arity;
+        const int i0 = (int)((cur / span) * span);
+        int nch = (int)((g.W - i0 + stride - 1) / stride);
+        if (nch > g.arity) nch = g.arity;
+        if (nch <= 1) continue;  // unpaired: carried up unchanged
+        if (lev > 1) {
+            pub_wait();  // this workgroup's slab stores have landed
+            __syncthreads();
+            if (tid == 0) s_old = atomicAdd(cnt + (((int64_t)(lev - 2) * g.W + i0) * ngroups + grp), 1);
+            __syncthreads();
+            if (s_old != nch - 1) return;
+        }
+        const int64_t sa = chain_start(g, i0);
+        SAcc<S, C> sl[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (colall) sl[p][i] = pub_load_off(B + (sa + 16 * p) * ldb, boff[i]);
+                else sl[p][i] = colok ? pub_load(B + (sa + 16 * p + M::orow(l4, i)) * ldb + col) : S(0);
+            }
+        for (int t = 1; t < nch; ++t) {
+            const int64_t ch = i0 + t * stride;
+            S* Bc = B + chain_start(g, (int)ch) * ldb;
+            // stage Y_node (64 x 64, row-major) and T_node
+            S ys[YS], ts[TSF];
+            const S* Yc = Ynode + ch * 4096;
+            const S* Tc = Tnode + ch * W_TRI;
+#pragma unroll
+            for (int u = 0; u < YS; ++u) ys[u] = Yc[(TW * u + wv) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < TSF; ++u) {
+                const int e = tid + NT * u, i = e >> 6, j = e & 63;
+                ts[u] = (i <= j) ? Tc[j * (j + 1) / 2 + i] : S(0);
+            }
+            S x[16];
+            if (colall) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) x[kk] = pub_load_off(Bc + 16 * (kk >> 2) * ldb, boff[kk & 3]);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) x[kk] = colok ? pub_load(Bc + xrow(kk) * ldb + col) : S(0);
+            }
+            if (staged) __syncthreads();  // every wave is done with the previous step's operands
+#pragma unroll
+            for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
+#pragma unroll
+            for (int u = 0; u < TSF; ++u) {
+                const int e = tid + NT * u;
+                sm.Tn[e >> 6][e & 63] = -(C)ts[u];
+            }
+            __syncthreads();
+            staged = true;
+            // W = S + Y^T X;  W' = T^T W (negated);  S -= W';  X -= Y W'
+            acc_t w[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                w[p] = vcvt<acc_t>(sl[p]);
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk)
+                    if ((kk >> 2) <= p) w[p] = M::mma(sm.Y[xrow(kk)][16 * p + l16], (C)x[kk], w[p]);
+                if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
+            }
+            acc_t nw[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                nw[p] = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q <= p; ++q)
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        nw[p] = M::mma(sm.Tn[16 * q + M::orow(l4, kc)][16 * p + l16], w[q][kc], nw[p]);
+                if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                acc_t u = kMixed<S, C> ? acc_t{0, 0, 0, 0}
+                                       : acc_t{(C)x[4 * r], (C)x[4 * r + 1], (C)x[4 * r + 2], (C)x[4 * r + 3]};
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? x[4 * r + i] + (S)u[i] : (S)u[i];
+                if constexpr (TW == 4) __builtin_amdgcn_sched_barrier(0);
+            }
+            if (colall) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) st_off(Bc + 16 * (kk >> 2) * ldb, boff[kk & 3], x[kk]);
+            } else if (colok) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) Bc[xrow(kk) * ldb + col] = x[kk];
+            }
+        }
+        if (colall) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pub_store_off(B + (sa + 16 * p) * ldb, boff[i], (S)sl[p][i]);
+        } else if (colok) {
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -941,7 +1118,7 @@ static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ld
     if (wide && tw == 4)
         k_qt_tree_w<S, C, 4><<<gridt, 256, 0, st>>>(g, ntiles, B, ldb, k, Yn, Tn, cnt);
     else if (wide)
-        k_qt_tree_w<S, C, 2><<<gridt, 128, 0, st>>>(g, ntiles, B, ldb, k, Yn, Tn, cnt);
+        k_qt_tree_w2<S, C, 2><<<gridt, 128, 0, st>>>(g, ntiles, B, ldb, k, Yn, Tn, cnt);
     else
         k_qt_tree64<S, C, NP><<<(unsigned)(nodes * ntiles), 256, 0, st>>>(g, ntiles, B, ldb, k, (const S*)wk.Ynode,
                                                                            (const S*)wk.Tnode, cnt);
