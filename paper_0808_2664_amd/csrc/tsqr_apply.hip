@@ -1042,6 +1042,133 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
     }
 }
 
+// The explicit Q's tree levels (binary tree, n = 64) in one launch.  Top
+// down, a node's step maps its slab S to its children's slabs: with the
+// children's rows zero (the explicit Q starts from [I_n; 0]), child 0 gets
+// S - W' and child 1 gets -Y W', W' = T S.  So the slab arriving at a level-1
+// node depends only on the steps along the path from the member's root, and
+// each workgroup (level-1 node, 16 TW columns) recomputes its own path from
+// S = I: every step along a path is the same arithmetic as in
+// k_node_apply_w, so the slabs are the same bits, and the ten levels cost
+// ten steps of one workgroup instead of ten dependent launches.  Only the
+// level-1 slabs are written (the two chains' top rows), so no workgroup
+// reads what another writes.
+template <typename S, typename C, int TW>
+__global__ __launch_bounds__(64 * TW, 2) void k_formq_paths_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
+                                                              int64_t k, const S* __restrict__ Ynode,
+                                                              const S* __restrict__ Tnode) {
+    constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
+    typedef Mfma<C> M;
+    typedef typename M::acc acc_t;
+    __shared__ WideSmem<C> sm;
+    const int node1 = blockIdx.x / ngroups;
+    const int grp = blockIdx.x - node1 * ngroups;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int64_t col = (int64_t)grp * (16 * TW) + 16 * wv + l16;
+    const bool colok = col < k;
+    auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
+    const int c1 = 2 * node1;
+    if (c1 >= g.W) return;
+    // the member's root slab: I_n
+    SAcc<S, C> sl[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sl[p][i] = (16 * p + M::orow(l4, i) == col) ? S(1) : S(0);
+    bool staged = false;
+    for (int lev = g.levels; lev >= 1; --lev) {
+        const int64_t stride = ipow(2, lev - 1), span = 2 * stride;
+        const int64_t i0 = (c1 / span) * span;
+        const int nch = (g.W - i0 > stride) ? 2 : 1;
+        const int t = (int)((c1 - i0) / stride);  // the child on this path (0 at level 1)
+        if (nch == 1) {
+            if (lev == 1 && colok) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        B[(chain_start(g, c1) + 16 * p + M::orow(l4, i)) * ldb + col] = (S)sl[p][i];
+            }
+            continue;  // unpaired: carried down unchanged
+        }
+        const int64_t ch = i0 + stride;
+        S ys[YS], ts[TSN];
+        const S* Yc = Ynode + ch * 4096;
+        const S* Tc = Tnode + ch * W_TRI;
+#pragma unroll
+        for (int u = 0; u < YS; ++u) ys[u] = Yc[(TW * u + wv) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < TSN; ++u) {
+            const int e = tid + NT * u;
+            ts[u] = (e < W_TRI) ? Tc[e] : S(0);
+        }
+        if (staged) __syncthreads();  // every wave is done with the previous step's operands
+#pragma unroll
+        for (int u = 0; u < YS; ++u) sm.Y[TW * u + wv][lane] = (C)ys[u];
+#pragma unroll
+        for (int u = 0; u < TSN; ++u) {
+            const int e = tid + NT * u;
+            if (e < W_TRI) sm.T[e] = (C)ts[u];
+        }
+        __syncthreads();
+        staged = true;
+        // W = S;  W' = T W (negated)
+        acc_t w[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) w[p] = vcvt<acc_t>(sl[p]);
+        acc_t nw[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            nw[p] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int q = p; q < 4; ++q)
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    const int ti = 16 * q + M::orow(l4, kc);
+                    const int tj = 16 * p + l16;
+                    const C a = (tj <= ti) ? wide_t(sm, tj, ti) : C(0);
+                    nw[p] = M::mma(-a, w[q][kc], nw[p]);
+                }
+        }
+        // child 1: X = -Y W' (the product of k_node_apply_w with X = 0)
+        S x[16];
+        const bool want1 = (lev == 1) || (t == 1);
+        if (want1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                acc_t u = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        if (p >= r) u = M::mma(sm.Y[16 * r + l16][16 * p + M::orow(l4, kc)], nw[p][kc], u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[4 * r + i] = kMixed<S, C> ? S(0) + (S)u[i] : (S)u[i];
+            }
+        }
+        // child 0: S - W'
+#pragma unroll
+        for (int p = 0; p < 4; ++p) sl[p] += vcvt<SAcc<S, C>>(nw[p]);
+        if (lev == 1) {
+            if (colok) {
+                S* B0 = B + chain_start(g, c1) * ldb;
+                S* B1 = B + chain_start(g, c1 + 1) * ldb;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) B0[(16 * p + M::orow(l4, i)) * ldb + col] = (S)sl[p][i];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) B1[xrow(kk) * ldb + col] = x[kk];
+            }
+        } else if (t == 1) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sl[p][i] = x[4 * p + i];
+        }
+    }
+}
+
 __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -1216,7 +1343,20 @@ static hipError_t apply_mode(const Geom& g, const S* Y, int64_t ldy, const Work&
         e = chain_apply_h<S, C, NC, MODE>(g, Y, ldy, wk, B, ldb, k, st);
         if (e == hipSuccess) e = qt_tree_launch<S, C, NC>(g, wk, B, ldb, k, st);
     } else {
-        for (int lev = g.levels; lev >= 1 && e == hipSuccess; --lev)
+        bool done = false;
+        if constexpr (MODE == MODE_FORMQ && NC == 64 && !kMixed<S, C>) {
+            // the explicit Q's binary tree: every level in one launch (paths)
+            if (g.levels >= 1 && g.arity == 2 && use_wide(g, k) && k > 32) {
+                const int ngroups = (int)((k + 63) / 64);
+                const int64_t gw = (int64_t)((g.W + 1) / 2) * ngroups;
+                if (gw > 0x7fffffff) return hipErrorInvalidValue;
+                k_formq_paths_w<S, C, 4><<<(unsigned)gw, 256, 0, st>>>(g, ngroups, B, ldb, k, (const S*)wk.Ynode,
+                                                                       (const S*)wk.Tnode);
+                e = hipGetLastError();
+                done = true;
+            }
+        }
+        for (int lev = g.levels; !done && lev >= 1 && e == hipSuccess; --lev)
             e = node_apply_launch<S, C, NC, MODE>(g, lev, wk, B, ldb, k, st);
         if (e == hipSuccess) e = chain_apply_h<S, C, NC, MODE>(g, Y, ldy, wk, B, ldb, k, st);
     }
