@@ -73,7 +73,8 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                min(number of blocks, 1024).  chains = number of blocks
  *                gives the plain parallel TSQR of Eqs. TSQR_binarytree_1..4.
  *   arity      : fan-in of the tree over the chain R factors (default 2).
- *   flags      : 0, TSQR_FLAG_TREE_LEVELWISE, TSQR_FLAG_ONE_WAVE or both.
+ *   flags      : 0 or any of TSQR_FLAG_TREE_LEVELWISE, TSQR_FLAG_ONE_WAVE,
+ *                TSQR_FLAG_SHARED_CUS.
  *                TSQR_FLAG_ONE_WAVE: every chain on the one-wave engine
  *                (chains and tree in one launch) also where the default is
  *                the two-wave chain engine (FP64, more than 32 columns:
@@ -87,6 +88,16 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                each node starts when its children are complete.  Both give
  *                the same bits; only the schedule differs (Sec. 2.1: the
  *                tree shape and order are free).
+ *                TSQR_FLAG_SHARED_CUS (caqr_factor only; ignored
+ *                elsewhere): by default, on a whole MI355X (256 CUs), once
+ *                the trailing columns are few (8192 with the FP64 update,
+ *                12288 with FP32 products), caqr_factor runs its panel
+ *                factorisations on one to four compute units of every XCD
+ *                (two chain workgroups of the first panel per unit) and its
+ *                trailing updates on the other units, through two CU-masked
+ *                streams of its own that it keeps until the process ends;
+ *                with this flag both always run on every unit.  Same bits
+ *                either way.
  *   max_polls  : in the panel-by-panel tree a wave waits for its children's
  *                progress, polling at most this many times (default 2^22,
  *                far beyond any real wait).  A wave that gives up sets the
@@ -99,7 +110,8 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  * tuning inputs. */
 #define TSQR_FLAG_TREE_LEVELWISE 1
 #define TSQR_FLAG_ONE_WAVE 2
-#define TSQR_FLAGS_ALL (TSQR_FLAG_TREE_LEVELWISE | TSQR_FLAG_ONE_WAVE)
+#define TSQR_FLAG_SHARED_CUS 4
+#define TSQR_FLAGS_ALL (TSQR_FLAG_TREE_LEVELWISE | TSQR_FLAG_ONE_WAVE | TSQR_FLAG_SHARED_CUS)
 typedef struct tsqr_opts {
     int32_t block_rows;
     int32_t chains;

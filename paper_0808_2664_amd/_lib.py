@@ -24,6 +24,7 @@ TSQR_ERR_SCRATCH = 6
 TSQR_MAX_N = 64
 TSQR_FLAG_TREE_LEVELWISE = 1
 TSQR_FLAG_ONE_WAVE = 2
+TSQR_FLAG_SHARED_CUS = 4
 
 
 class TsqrOpts(ctypes.Structure):

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/tsqr.h"
@@ -434,6 +435,56 @@ int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
     return apply_one(q, q->n, Q, ldq, tsqr::MODE_FORMQ, q->f64, st);
 }
 
+// CAQR's split of the device between its two streams: the panel
+// factorisations (a few dozen latency-bound workgroups, on the critical path
+// whenever the trailing update is short) run on r compute units of every XCD
+// and the trailing updates on the others, so that a panel kernel never waits
+// for CU slots held by update workgroups nor shares a SIMD with their MFMA
+// work.  Only on a whole MI355X (256 CUs in 8 XCDs), where bit i of a
+// stream's CU mask selects a CU of XCD i mod 8 (read back from the XCC_ID
+// register of the workgroups of masked streams): bits 0 .. 8r - 1 give r CUs
+// on every XCD, and every XCD keeps CUs in both masks.  The streams are made
+// once per device and r and kept until the process ends.
+static bool caqr_split_streams(int r, hipStream_t* upd, hipStream_t* fac) {
+    constexpr int kCUs = 256, kXCDs = 8, kMaxR = 4;
+    if (r < 1 || r > kMaxR) return false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    static std::mutex mu;
+    static hipStream_t cache[64][kMaxR][2];
+    static bool tried[64][kMaxR];
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[dev][r - 1]) {
+        tried[dev][r - 1] = true;
+        int cus = 0;
+        hipDeviceProp_t prop;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (cus != kCUs || strncmp(prop.gcnArchName, "gfx950", 6) != 0) return false;
+        uint32_t mask_f[kCUs / 32], mask_u[kCUs / 32];
+        for (int w = 0; w < kCUs / 32; ++w) mask_f[w] = mask_u[w] = 0;
+        for (int i = 0; i < kCUs; ++i) {
+            uint32_t* m = (i < kXCDs * r) ? mask_f : mask_u;
+            m[i / 32] |= 1u << (i % 32);
+        }
+        hipStream_t su = nullptr, sf = nullptr;
+        if (hipExtStreamCreateWithCUMask(&su, kCUs / 32, mask_u) != hipSuccess ||
+            hipExtStreamCreateWithCUMask(&sf, kCUs / 32, mask_f) != hipSuccess) {
+            (void)hipGetLastError();
+            if (su) (void)hipStreamDestroy(su);
+            return false;
+        }
+        cache[dev][r - 1][0] = su;
+        cache[dev][r - 1][1] = sf;
+    }
+    *upd = cache[dev][r - 1][0];
+    *fac = cache[dev][r - 1][1];
+    return *upd != nullptr && *fac != nullptr;
+}
+
 int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int update_dtype,
                 const tsqr_opts* opts, tsqr_qtree* q_out, void* stream) {
     if (!check_dtype(dtype)) return -1;
@@ -470,16 +521,6 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // hides only behind a long enough update): eight blocks for panels of
     // 12288 rows or more, four below (measured on 8192^2 and 16384^2), node
     // by node (no waiting on a stream shared with the update).
-    hipStream_t s2 = nullptr;
-    hipEvent_t ev_head = nullptr, ev_fact = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_head, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming);
-    auto cleanup = [&]() {
-        if (ev_head) (void)hipEventDestroy(ev_head);
-        if (ev_fact) (void)hipEventDestroy(ev_fact);
-        if (s2) (void)hipStreamDestroy(s2);
-    };
     auto panel_opts = [&](int64_t rows) {
         tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0, 0};
         if (o.chains == 0) {
@@ -496,6 +537,40 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         o.flags |= TSQR_FLAG_TREE_LEVELWISE;
         return o;
     };
+    // The update stream su and the panel stream s2: the caller's stream and a
+    // second stream while the trailing updates are long (they need every
+    // unit; the panel hides behind them), then the CU-masked pair that splits
+    // the device (two workgroups of the first panel's chain kernel per
+    // reserved unit) once the trailing columns are few enough for the panel
+    // factorisation to be on the critical path.
+    hipStream_t su = st, s2 = nullptr, mu = nullptr, mf = nullptr;
+    bool masked = false;
+    if (!(opts && (opts->flags & TSQR_FLAG_SHARED_CUS)) && n > panel) {
+        Geom g0;
+        const tsqr_opts o0 = panel_opts(m);
+        if (tsqr::make_geom(m, n < panel ? n : panel, &o0, &g0) == 0) {
+            const int r = (g0.W + 15) / 16;
+            masked = caqr_split_streams(r < 1 ? 1 : (r > 4 ? 4 : r), &mu, &mf);
+        }
+    }
+    // the switch point, in trailing columns (16384^2: 8192 with the FP64
+    // update, 12288 with FP32 products; the whole run masked loses 4 ms and
+    // gains 8, none masked loses 7 and 8; 8192^2: masked throughout is best)
+    const int64_t split_cols = cf64 ? 8192 : 12288;
+    hipEvent_t ev_head = nullptr, ev_fact = nullptr, ev_in = nullptr, ev_sw = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+    hipStream_t s2_own = s2;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_head, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_sw, hipEventDisableTiming);
+    auto cleanup = [&]() {
+        if (ev_head) (void)hipEventDestroy(ev_head);
+        if (ev_fact) (void)hipEventDestroy(ev_fact);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_sw) (void)hipEventDestroy(ev_sw);
+        if (s2_own) (void)hipStreamDestroy(s2_own);
+    };
     auto factor_panel = [&](int64_t r0, hipStream_t fs) -> int {
         const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
         const int64_t rows = m - r0;
@@ -508,17 +583,42 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         q->panels.push_back(pq);
         return 0;
     };
-    int rc = (e == hipSuccess) ? factor_panel(0, st) : hip_fail(e);
+    // switch to the masked pair: it starts after everything issued so far
+    // (su has already waited for the last panel factorisation on s2)
+    auto go_masked = [&]() -> hipError_t {
+        hipError_t err = hipEventRecord(ev_sw, su);
+        if (err == hipSuccess) err = hipStreamWaitEvent(mu, ev_sw, 0);
+        if (err == hipSuccess) err = hipStreamWaitEvent(mf, ev_sw, 0);
+        su = mu;
+        s2 = mf;
+        return err;
+    };
+    if (e == hipSuccess && masked && n - (n < panel ? n : panel) <= split_cols) e = go_masked();
+    // the first panel is factored on s2 after the caller's earlier work
+    if (e == hipSuccess && su == st) {
+        e = hipEventRecord(ev_in, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev_in, 0);
+    }
+    int rc = (e == hipSuccess) ? factor_panel(0, s2) : hip_fail(e);
+    if (rc == 0) {
+        e = hipEventRecord(ev_fact, s2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(su, ev_fact, 0);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
     for (int64_t r0 = 0; rc == 0 && r0 < n; r0 += panel) {
         const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
         const int64_t tc = n - r0 - cols;
         if (tc <= 0) break;
+        if (masked && su == st && tc <= split_cols) {
+            e = go_masked();
+            if (e != hipSuccess) { rc = hip_fail(e); break; }
+        }
         tsqr_qtree_s* pq = q->panels.back();
         char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
         char* Bt = P + (size_t)cols * es;
         const int64_t head = tc < panel ? tc : panel;  // the next panel's columns
-        e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, Bt, lda, head, tsqr::MODE_QT, st);
-        if (e == hipSuccess) e = hipEventRecord(ev_head, st);
+        e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, Bt, lda, head, tsqr::MODE_QT, su);
+        if (e == hipSuccess) e = hipEventRecord(ev_head, su);
         if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev_head, 0);
         if (e != hipSuccess) { rc = hip_fail(e); break; }
         rc = factor_panel(r0 + cols, s2);
@@ -526,9 +626,15 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         e = hipEventRecord(ev_fact, s2);
         if (e == hipSuccess && tc > head)
             e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, Bt + (size_t)head * es, lda, tc - head,
-                                   tsqr::MODE_QT, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_fact, 0);
+                                   tsqr::MODE_QT, su);
+        if (e == hipSuccess) e = hipStreamWaitEvent(su, ev_fact, 0);
         if (e != hipSuccess) rc = hip_fail(e);
+    }
+    // the caller's stream resumes after every panel and update
+    if (su != st) {
+        e = hipEventRecord(ev_sw, su);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_sw, 0);
+        if (e != hipSuccess && rc == 0) rc = hip_fail(e);
     }
     cleanup();
     if (rc != 0) {

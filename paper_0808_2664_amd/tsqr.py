@@ -252,17 +252,20 @@ def sign_normalize(Q: torch.Tensor | None, R: torch.Tensor):
     return Q, R
 
 
-def caqr(A: torch.Tensor, panel: int = 64, update=None, block_rows=0, chains=0, arity=0):
+def caqr(A: torch.Tensor, panel: int = 64, update=None, block_rows=0, chains=0, arity=0, shared_cus=False):
     """CAQR of A (m x n, m >= n), IN PLACE.  `update` is the dtype of the
     trailing-update arithmetic (default: A's dtype; torch.float32 with a
-    float64 A gives the mixed-precision update).  Returns (R, QTree) with R
-    the upper triangle of A's first n rows (a copy)."""
+    float64 A gives the mixed-precision update).  shared_cus: panels and
+    updates on every compute unit (TSQR_FLAG_SHARED_CUS) instead of a few
+    units per XCD reserved for the panels; same bits.  Returns (R, QTree)
+    with R the upper triangle of A's first n rows (a copy)."""
     lib = _lib.load()
     m, n = A.shape
     upd = _dtype_code(A) if update is None else (_lib.TSQR_F64 if update == torch.float64 else _lib.TSQR_F32)
     h = ctypes.c_void_p()
     rc = lib.caqr_factor(_dtype_code(A), m, n, _ptr(A), _ld(A), panel, upd,
-                         _opts(block_rows, chains, arity), ctypes.byref(h), _stream(A))
+                         _opts(block_rows, chains, arity, _lib.TSQR_FLAG_SHARED_CUS if shared_cus else 0),
+                         ctypes.byref(h), _stream(A))
     _lib.check("caqr_factor", rc)
     R = torch.empty(n, n, dtype=A.dtype, device=A.device)
     _lib.check("tsqr_copy_r", lib.tsqr_copy_r(_dtype_code(A), n, _ptr(A), _ld(A), _ptr(R), _ld(R), _stream(A)))

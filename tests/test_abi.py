@@ -53,7 +53,7 @@ def test_factor_argument_errors_without_launch():
     assert f(1, 100, 4, None, 4, fake, 4, None, ctypes.byref(h), None) == -4       # A
     assert f(1, 100, 4, fake, 3, fake, 4, None, ctypes.byref(h), None) == -5       # lda
     assert f(1, 100, 4, fake, 4, fake, 3, None, ctypes.byref(h), None) == -7       # ldr
-    bad = _lib.opts(flags=4)  # not a defined flag
+    bad = _lib.opts(flags=8)  # not a defined flag
     assert f(1, 100, 4, fake, 4, fake, 4, ctypes.byref(bad), ctypes.byref(h), None) == -8
     assert f(1, 100, 4, fake, 4, None, 4, None, None, None) == -9                  # nothing to return
     bad_h = _lib.opts(block_rows=100)
@@ -147,7 +147,7 @@ def test_lstsq_argument_errors_without_launch():
     assert f(1, 100, 4, fake, 4, -1, fake, 2, None, None, None) == -6          # k
     assert f(1, 100, 4, fake, 4, 2, None, 2, None, None, None) == -7           # B
     assert f(1, 100, 4, fake, 4, 2, fake, 1, None, None, None) == -8           # ldb
-    bad = _lib.opts(flags=4)
+    bad = _lib.opts(flags=8)
     assert f(1, 100, 4, fake, 4, 2, fake, 2, None, ctypes.byref(bad), None) == -10
 
 

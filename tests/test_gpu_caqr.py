@@ -155,3 +155,28 @@ def test_caqr_config3_full_size_against_oracle():
           % (e64, e32, errs[torch.float64], errs[torch.float32]))
     assert e64 <= 1e-11 and errs[torch.float64] <= 1e-13
     assert 1e-12 < e32 <= 1e-4 and errs[torch.float32] <= 1e-4
+
+
+@pytest.mark.parametrize("upd", [torch.float64, torch.float32])
+def test_caqr_cu_split_same_bits(upd):
+    """The default schedule (panels on a few reserved CUs per XCD once the
+    trailing columns are few, which here is from the first panel) and
+    TSQR_FLAG_SHARED_CUS (every kernel on every CU) give the same bits: the
+    reflectors and R in A, and Q^T applied to a block of columns."""
+    import paper_0808_2664_amd as tq
+    m, n = 3000, 1536
+    _note("case: caqr cu split vs shared %d x %d update=%s" % (m, n, upd))
+    A = workloads.gaussian(m, n, 808)
+    outs = []
+    for shared in (False, True):
+        Ad = _dev(A)
+        R, qt = tq.caqr(Ad, panel=64, update=upd, shared_cus=shared)
+        torch.cuda.synchronize()
+        outs.append((Ad.clone(), R.clone()))
+        qt.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    Ro = _oracle_r(A)
+    e = _r_err(outs[0][1], Ro)
+    _note("  R error %.2e" % e)
+    assert e <= (1e-11 if upd == torch.float64 else 1e-4)
