@@ -60,6 +60,10 @@ def parse():
                    help="skip the batched, CAQR and forward+backward measurements")
     p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "config1", "lstsq", "cholqr"), default=None,
                    help="run only this measurement and print its JSON (for profiling it)")
+    p.add_argument("--no-oracle", action="store_true",
+                   help="with --extra caqr: skip the host oracle's R (for profiling the GPU part alone)")
+    p.add_argument("--caqr-reps", type=int, default=10,
+                   help="timed CAQR factorisations per update type (median reported)")
     return p.parse_args()
 
 
@@ -153,7 +157,11 @@ def main():
         import paper_0808_2664_amd as tq_x
         fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "config1": bench_config1,
               "lstsq": bench_lstsq, "cholqr": bench_cholqr}[a.extra]
-        print(json.dumps({a.extra: fn(tq_x, torch, np)}), flush=True)
+        if a.extra == "caqr":
+            res = bench_caqr(tq_x, torch, np, oracle_check=not a.no_oracle, reps=max(1, a.caqr_reps))
+        else:
+            res = fn(tq_x, torch, np)
+        print(json.dumps({a.extra: res}), flush=True)
         return
 
     import workloads
@@ -254,7 +262,7 @@ def main():
         for name, fn in (("caqr", bench_caqr), ("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd),
                          ("config1", bench_config1), ("lstsq", bench_lstsq), ("cholqr", bench_cholqr)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
-            extras[name] = fn(tq, torch, np)
+            extras[name] = bench_caqr(tq, torch, np, reps=max(1, a.caqr_reps)) if name == "caqr" else fn(tq, torch, np)
             torch.cuda.empty_cache()
     names = ("factor", "apply_qt", "form_q")
     phases = {}
@@ -368,11 +376,12 @@ def bench_batched(tq, torch, np):
     return res
 
 
-def bench_caqr(tq, torch, np, oracle_check=True):
+def bench_caqr(tq, torch, np, oracle_check=True, reps=10):
     """Config 3: CAQR of a 16384 x 16384 N(0,1) matrix (seed 5, drawn with
     numpy on the host and copied to the device once), panel 64, trailing
     updates in FP64 and with FP32 products on FP64 storage.  Time: median of
-    10 factorisations each (each on a fresh copy of A).  Errors per result:
+    `reps` factorisations each (10 unless --caqr-reps; each on a fresh copy of
+    A, after one untimed factorisation).  Errors per result:
     backward error ||A - QR||/||A|| through the GPU's implicit Q, and the
     normwise error of the sign-normalised R against the oracle's blocked
     Householder QR of the same matrix (run on the host after the timings)."""
@@ -400,7 +409,6 @@ def bench_caqr(tq, torch, np, oracle_check=True):
         run()
         box["qt"].close()
         ts = []
-        reps = 10
         for r in range(reps):
             run()
             ts.append(box["ms"])
