@@ -345,6 +345,14 @@ int tsqr_copy_r(int dtype, int64_t n, const void* src, int64_t lds, void* dst, i
  * safe.  Errors: 1 phase. */
 int tsqr_set_phase_events(int phase, void* start, void* stop);
 
+/* Release the CU-masked streams caqr_factor keeps (see TSQR_FLAG_SHARED_CUS)
+ * on every device where it made them, after waiting for their work; a later
+ * caqr_factor makes them again.  For callers that want no library-held
+ * stream left at process exit (the Python binding calls it from an exit
+ * handler).  Not to be called while a caqr_factor is running.  Errors:
+ * TSQR_ERR_HIP. */
+int tsqr_release_streams(void);
+
 /* Last HIP error code seen by this thread (0 if none) and a message. */
 int tsqr_last_hip_error(void);
 const char* tsqr_status_string(int status);

@@ -6,6 +6,7 @@ fails loudly (there is no CPU fallback).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -93,6 +94,7 @@ def load():
         "tsqr_batch_factor": [vp, vp, vp, vp, vp, vp],
         "tsqr_batch_plan_info": [vp, p64],
         "tsqr_batch_plan_destroy": [vp],
+        "tsqr_release_streams": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -103,7 +105,17 @@ def load():
     lib.tsqr_status_string.argtypes = [ctypes.c_int]
     lib.tsqr_status_string.restype = ctypes.c_char_p
     _lib = lib
+    atexit.register(_release_at_exit)
     return lib
+
+
+def _release_at_exit():
+    # no library-held CU-masked stream left when the process ends
+    if _lib is not None:
+        try:
+            _lib.tsqr_release_streams()
+        except Exception:
+            pass
 
 
 def check(func: str, code: int):

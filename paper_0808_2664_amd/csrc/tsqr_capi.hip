@@ -456,15 +456,19 @@ int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
 // (16384^2 FP64 update: 311 against 268 ms shared, 261 split in a process
 // without that launch; also with the pair made ahead of the launch, or made
 // per call), so such a process keeps every kernel on every unit.
+constexpr int kSplitMaxR = 4;
+static std::mutex g_split_mu;
+static hipStream_t g_split_cache[64][kSplitMaxR][2];
+static bool g_split_tried[64][kSplitMaxR];
+
 static bool caqr_split_streams(int r, hipStream_t* upd, hipStream_t* fac) {
-    constexpr int kCUs = 256, kXCDs = 8, kMaxR = 4;
+    constexpr int kCUs = 256, kXCDs = 8, kMaxR = kSplitMaxR;
     if (r < 1 || r > kMaxR) return false;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
-    static std::mutex mu;
-    static hipStream_t cache[64][kMaxR][2];
-    static bool tried[64][kMaxR];
-    std::lock_guard<std::mutex> lock(mu);
+    auto& cache = g_split_cache;
+    auto& tried = g_split_tried;
+    std::lock_guard<std::mutex> lock(g_split_mu);
     if (!tried[dev][r - 1]) {
         tried[dev][r - 1] = true;
         if (tsqr::g_coop_seen.load(std::memory_order_relaxed)) return false;
@@ -495,6 +499,34 @@ static bool caqr_split_streams(int r, hipStream_t* upd, hipStream_t* fac) {
     *upd = cache[dev][r - 1][0];
     *fac = cache[dev][r - 1][1];
     return *upd != nullptr && *fac != nullptr;
+}
+
+int tsqr_release_streams(void) {
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    bool any = false;  // no HIP call at all when none was made
+    for (int dev = 0; dev < 64 && !any; ++dev)
+        for (int r = 0; r < kSplitMaxR; ++r) any = any || g_split_cache[dev][r][0] || g_split_cache[dev][r][1];
+    if (!any) return 0;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return hip_fail(hipGetLastError());
+    hipError_t first = hipSuccess;
+    for (int dev = 0; dev < 64; ++dev)
+        for (int r = 0; r < kSplitMaxR; ++r) {
+            hipStream_t* p = g_split_cache[dev][r];
+            if (!p[0] && !p[1]) continue;
+            hipError_t e = hipSetDevice(dev);
+            for (int k = 0; k < 2 && e == hipSuccess; ++k)
+                if (p[k]) {
+                    e = hipStreamSynchronize(p[k]);
+                    if (e == hipSuccess) e = hipStreamDestroy(p[k]);
+                    p[k] = nullptr;
+                }
+            if (e != hipSuccess && first == hipSuccess) first = e;
+            g_split_tried[dev][r] = false;
+        }
+    hipError_t e = hipSetDevice(cur);
+    if (first == hipSuccess) first = e;
+    return first == hipSuccess ? 0 : hip_fail(first);
 }
 
 int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int update_dtype,
