@@ -565,7 +565,17 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // hides only behind a long enough update): eight blocks for panels of
     // 12288 rows or more, four below (measured on 8192^2 and 16384^2), node
     // by node (no waiting on a stream shared with the update).
-    auto panel_opts = [&](int64_t rows) {
+    // the switch point to the split device (below), in trailing columns
+    // (16384^2: 8192 with the FP64 update, 12288 with FP32 products; the
+    // whole run split loses 4 ms and gains 8, none split loses 7 and 8;
+    // 8192^2: split throughout is best)
+    const int64_t split_cols = cf64 ? 8192 : 12288;
+    // early: a panel factored before the switch point (whether or not the
+    // device is then split, so that both schedules factor the same trees)
+    auto early_panel = [&](int64_t r1) {
+        return r1 == 0 ? (n - (n < panel ? n : panel) > split_cols) : (n - r1 > split_cols);
+    };
+    auto panel_opts = [&](int64_t rows, bool early) {
         tsqr_opts o = opts ? *opts : tsqr_opts{0, 0, 0, 0, 0};
         if (o.chains == 0) {
             const int64_t blocks = (rows + 63) / 64;
@@ -573,8 +583,14 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
             // panels under 12288 rows take four so that their factor (on the
             // critical path near the end) stays short, except with the FP32
             // update on matrices of 12288 columns or more, where eight is
-            // faster for every panel (measured at 8192, 12288 and 16384)
-            const int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288)) ? 8 : 4;
+            // faster for every panel (measured at 8192, 12288 and 16384).
+            // Before the switch point, where the update is long, panels of
+            // 12288 rows or more take sixteen: half the update's tree steps again,
+            // the longer panel factor hidden behind the update (16384^2: FP64
+            // 261.1 -> 257.1 ms, FP32 products 215.4 -> 207.2 ms; twelve and
+            // twenty, trees that are not powers of two, were slower)
+            int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288)) ? 8 : 4;
+            if (early && rows >= 12288) chain_blocks = 16;
             const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
         }
@@ -591,16 +607,12 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     bool masked = false;
     if (!(opts && (opts->flags & TSQR_FLAG_SHARED_CUS)) && n > panel) {
         Geom g0;
-        const tsqr_opts o0 = panel_opts(m);
+        const tsqr_opts o0 = panel_opts(m, early_panel(0));
         if (tsqr::make_geom(m, n < panel ? n : panel, &o0, &g0) == 0) {
             const int r = (g0.W + 15) / 16;
             masked = caqr_split_streams(r < 1 ? 1 : (r > 4 ? 4 : r), &mu, &mf);
         }
     }
-    // the switch point, in trailing columns (16384^2: 8192 with the FP64
-    // update, 12288 with FP32 products; the whole run masked loses 4 ms and
-    // gains 8, none masked loses 7 and 8; 8192^2: masked throughout is best)
-    const int64_t split_cols = cf64 ? 8192 : 12288;
     hipEvent_t ev_head = nullptr, ev_fact = nullptr, ev_in = nullptr, ev_sw = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
     hipStream_t s2_own = s2;
@@ -619,7 +631,7 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
         const int64_t rows = m - r0;
         char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
-        tsqr_opts po = panel_opts(rows);
+        tsqr_opts po = panel_opts(rows, early_panel(r0));
         tsqr_qtree_s* pq = nullptr;
         int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, &po, &pq, fs);
         if (rc != 0) return rc == -1 ? -2 : rc;
