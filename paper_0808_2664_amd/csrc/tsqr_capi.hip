@@ -583,13 +583,14 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
             // panels under 12288 rows take four so that their factor (on the
             // critical path near the end) stays short, except with the FP32
             // update on matrices of 12288 columns or more, where eight is
-            // faster for every panel (measured at 8192, 12288 and 16384).
+            // faster down to 8192 rows (12288^2: 121.6 -> 118.1 ms, 16384^2:
+            // 206.2 -> 203.7 ms against eight for every panel).
             // Before the switch point, where the update is long, panels of
             // 12288 rows or more take sixteen: half the update's tree steps again,
             // the longer panel factor hidden behind the update (16384^2: FP64
             // 261.1 -> 257.1 ms, FP32 products 215.4 -> 207.2 ms; twelve and
             // twenty, trees that are not powers of two, were slower)
-            int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288)) ? 8 : 4;
+            int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288 && rows >= 8192)) ? 8 : 4;
             if (early && rows >= 12288) chain_blocks = 16;
             const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
