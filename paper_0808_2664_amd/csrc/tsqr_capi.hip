@@ -580,17 +580,20 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         if (o.chains == 0) {
             const int64_t blocks = (rows + 63) / 64;
             // eight-block chains halve the update's tree steps against four;
-            // panels under 12288 rows take four so that their factor (on the
-            // critical path near the end) stays short, except with the FP32
-            // update on matrices of 12288 columns or more, where eight is
-            // faster down to 8192 rows (12288^2: 121.6 -> 118.1 ms, 16384^2:
-            // 206.2 -> 203.7 ms against eight for every panel).
+            // shorter panels take four so that their factor (on the critical
+            // path near the end) stays short.  The switch: 6144 rows with the
+            // FP64 update (against 12288: 16384^2 255.7 -> 247.1 ms, 12288^2
+            // 140.7 -> 132.1 ms, 8192^2 61.0 -> 60.6 ms); with FP32 products
+            // 12288 rows, or 8192 on matrices of 12288 columns or more
+            // (12288^2: 121.6 -> 118.1 ms, 16384^2: 206.2 -> 203.7 ms against
+            // eight for every panel; 8192 on 8192^2 was slower).
             // Before the switch point, where the update is long, panels of
             // 12288 rows or more take sixteen: half the update's tree steps again,
             // the longer panel factor hidden behind the update (16384^2: FP64
             // 261.1 -> 257.1 ms, FP32 products 215.4 -> 207.2 ms; twelve and
             // twenty, trees that are not powers of two, were slower)
-            int chain_blocks = (rows >= 12288 || (!cf64 && n >= 12288 && rows >= 8192)) ? 8 : 4;
+            const bool eight = cf64 ? rows >= 6144 : (rows >= 12288 || (n >= 12288 && rows >= 8192));
+            int chain_blocks = eight ? 8 : 4;
             if (early && rows >= 12288) chain_blocks = 16;
             const int64_t w = (blocks + chain_blocks - 1) / chain_blocks;
             o.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
