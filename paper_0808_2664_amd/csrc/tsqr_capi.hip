@@ -219,10 +219,11 @@ static int factor_geom(int dtype, const Geom& g, void* A, int64_t lda, void* R, 
 
 static int factor_impl(int dtype, int64_t m, int64_t n, void* A, int64_t lda, void* R, int64_t ldr,
                        bool r_upper_only, const tsqr_opts* opts, tsqr_qtree_s** out, hipStream_t st,
-                       bool want_q = true) {
+                       bool want_q = true, int extra_gflags = 0) {
     Geom g;
     int rc = tsqr::make_geom(m, n, opts, &g);
     if (rc != 0) return rc;
+    g.flags |= extra_gflags;
     return factor_geom(dtype, g, A, lda, R, ldr, 0, r_upper_only, opts, out, st, want_q);
 }
 
@@ -609,12 +610,14 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // factorisation to be on the critical path.
     hipStream_t su = st, s2 = nullptr, mu = nullptr, mf = nullptr;
     bool masked = false;
+    int split_r = 0;  // reserved CUs per XCD
     if (!(opts && (opts->flags & TSQR_FLAG_SHARED_CUS)) && n > panel) {
         Geom g0;
         const tsqr_opts o0 = panel_opts(m, early_panel(0));
         if (tsqr::make_geom(m, n < panel ? n : panel, &o0, &g0) == 0) {
             const int r = (g0.W + 15) / 16;
-            masked = caqr_split_streams(r < 1 ? 1 : (r > 4 ? 4 : r), &mu, &mf);
+            split_r = r < 1 ? 1 : (r > 4 ? 4 : r);
+            masked = caqr_split_streams(split_r, &mu, &mf);
         }
     }
     hipEvent_t ev_head = nullptr, ev_fact = nullptr, ev_in = nullptr, ev_sw = nullptr;
@@ -636,8 +639,13 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
         const int64_t rows = m - r0;
         char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
         tsqr_opts po = panel_opts(rows, early_panel(r0));
+        // on the masked panel stream (its 8r units alone run the panel's
+        // kernels, in order) the tree is panel-pipelined with an ordinary
+        // launch when its waves fit one per SIMD there
+        int gflags = 0;
+        if (fs != s2_own && su != st && po.chains <= 32 * split_r) gflags = tsqr::TREE_PIPE_PLAIN;
         tsqr_qtree_s* pq = nullptr;
-        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, &po, &pq, fs);
+        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, &po, &pq, fs, true, gflags);
         if (rc != 0) return rc == -1 ? -2 : rc;
         pq->stream = st;  // later applies and the release run on the caller's stream
         q->panels.push_back(pq);

@@ -39,6 +39,11 @@ constexpr int TREE_LEVELWISE = 1;
 // Geom::flags: reduce every chain with the one-wave engine, also where the
 // two-wave chain engine applies (FP64, more than 32 columns).
 constexpr int ONE_WAVE = 2;
+// Geom::flags (set by the library only): the panel-pipelined tree with an
+// ordinary launch, its waves' residency guaranteed by the caller (CAQR's
+// panels on a CU-masked stream of their own, with at most one wave per SIMD
+// of its units); takes precedence over TREE_LEVELWISE.
+constexpr int TREE_PIPE_PLAIN = 4;
 
 // Chain c is chain c % cpm of member c / cpm; a member's last chain takes
 // the member's remaining rows.

@@ -57,6 +57,12 @@ template <typename T, int NP, int SG, bool WQ, bool CHAIN>
 static hipError_t launch_tree(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
     T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
     T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
+    const bool plain = (g.flags & TREE_PIPE_PLAIN) != 0;
+    if (plain && g.W > 1 && g.arity == 2) {
+        k_wave_tsqr<T, NP, SG, true, WQ, CHAIN><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode,
+                                                                    tau_node, ta);
+        return hipGetLastError();
+    }
     const bool pipe =
         g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ, CHAIN>();
     if (pipe) {
