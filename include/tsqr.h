@@ -213,6 +213,10 @@ int tsqr_sign_normalize_batched(int dtype, int64_t batch, int64_t m, int64_t n, 
  * of Q factors; "about the same cost as the traditionally represented Q").
  * B: device m x k (ldb >= k), in place.  Rows 0..n-1 then hold the thin
  * Q^T B (to the signs of diag R); rows n..m-1 depend on the tree shape.
+ * tsqr_apply_qt, tsqr_apply_q and tsqr_form_q only read the implicit Q (the
+ * tree steps' counters are stream-ordered allocations of each call), so
+ * calls on distinct B may run concurrently on different streams; the caller
+ * orders tsqr_qtree_destroy after all of them.
  * Errors: 1 q, 2 k, 3 B, 4 ldb. */
 int tsqr_apply_qt(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
 

@@ -356,3 +356,39 @@ def test_f32_wide_apply_against_oracle(k):
     np.testing.assert_allclose(tail, np.linalg.norm(full_o[n:], axis=0), rtol=1e-5)
     assert oracle.rel_err(back, B64) <= 1e-5  # Q (Q^T B) = B
     qt.close()
+
+
+def test_apply_qt_and_form_q_concurrent_streams():
+    """apply_qt and form_q on two streams at once (the benchmark's schedule)
+    give the same bits as one after the other, on 2^18 x 64 FP64 with 256
+    chains (wide apply kernels, tree kernels by last arrival), and Q^T B
+    matches the oracle's column norms."""
+    import paper_0808_2664_amd as tq
+    _note("case: apply_qt || form_q on two streams, 262144 x 64")
+    m, n, k = 1 << 18, 64, 32
+    A = workloads.gaussian(m, n, 920)
+    B = workloads.gaussian(m, k, 921)
+    Ad = _dev(A)
+    R, qt = tq.factor(Ad, chains=256)
+    B1, B2 = _dev(B), _dev(B)
+    Q1 = torch.empty(m, n, dtype=torch.float64, device="cuda")
+    Q2 = torch.empty_like(Q1)
+    qt.apply_qt(B1)
+    qt.form_q(Q1)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            qt.apply_qt(B2)
+        qt.form_q(Q2)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        assert torch.equal(Q1, Q2)
+        assert torch.equal(B1, B2)
+        B2.copy_(_dev(B))
+    torch.cuda.synchronize()
+    qt.close()
+    YRo, tauo = oracle.geqrf(A)
+    np.testing.assert_allclose(np.linalg.norm(B1[:n].cpu().numpy(), axis=0),
+                               np.linalg.norm(oracle.apply_qt(YRo, tauo, B)[:n], axis=0), rtol=1e-12)
