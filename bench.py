@@ -58,7 +58,8 @@ def parse():
                    help="rows of the bounded oracle sample for cpu_baseline (0 = skip)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, CAQR and forward+backward measurements")
-    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "config1", "lstsq", "cholqr"), default=None,
+    p.add_argument("--extra", choices=("batched", "caqr", "fwd_bwd", "config1", "lstsq", "cholqr", "caqr_left"),
+                   default=None,
                    help="run only this measurement and print its JSON (for profiling it)")
     p.add_argument("--no-oracle", action="store_true",
                    help="with --extra caqr: skip the host oracle's R (for profiling the GPU part alone)")
@@ -156,7 +157,7 @@ def main():
     if a.extra:
         import paper_0808_2664_amd as tq_x
         fn = {"batched": bench_batched, "caqr": bench_caqr, "fwd_bwd": bench_fwd_bwd, "config1": bench_config1,
-              "lstsq": bench_lstsq, "cholqr": bench_cholqr}[a.extra]
+              "lstsq": bench_lstsq, "cholqr": bench_cholqr, "caqr_left": bench_caqr_left}[a.extra]
         if a.extra == "caqr":
             res = bench_caqr(tq_x, torch, np, oracle_check=not a.no_oracle, reps=max(1, a.caqr_reps))
         else:
@@ -268,7 +269,8 @@ def main():
         cpu = cpu_baseline(min(a.cpu_rows, m), n, k)
     if not a.no_extras:
         for name, fn in (("batched", bench_batched), ("fwd_bwd", bench_fwd_bwd),
-                         ("config1", bench_config1), ("lstsq", bench_lstsq), ("cholqr", bench_cholqr)):
+                         ("config1", bench_config1), ("lstsq", bench_lstsq), ("cholqr", bench_cholqr),
+                         ("caqr_left", bench_caqr_left)):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn(tq, torch, np)
             torch.cuda.empty_cache()
@@ -452,6 +454,68 @@ def bench_caqr(tq, torch, np, oracle_check=True, reps=10):
             res[name]["R_error_vs_oracle"] = oracle.rel_err(R * oracle.signs(R)[:, None], Ro)
         res["oracle"] = {"kind": "blocked Householder QR, panels of 64, FP64", "threads": threads,
                          "seconds": round(time.perf_counter() - t0, 1)}
+    return res
+
+
+def bench_caqr_left(tq, torch, np):
+    """Left-looking CAQR over column blocks (Sec. 3.2), FP64 update, panel
+    64: on the 16384^2 N(0,1) matrix of the CAQR measurement (seed 5) with
+    blocks of 1024, 4096 and 16384 columns, and plain left-looking (blocks of
+    one panel) on a 4096^2 N(0,1) matrix (seed 11) beside right-looking CAQR
+    of the same matrix.  Median of 3 factorisations each (after one untimed);
+    per result the backward error through the GPU's implicit Q and the
+    normwise difference of the sign-normalised R from right-looking CAQR's
+    (the oracle comparison is in the GPU tests)."""
+    import workloads
+    res = {"workload": "left-looking CAQR over column blocks, FP64 storage and update, panel 64", "runs": 3}
+
+    def signed(R):
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1
+        return R * d[:, None]
+
+    def timed(A0, fn):
+        A = A0.clone()
+        ts = []
+        for r in range(4):
+            A.copy_(A0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            R, qt = fn(A)
+            e1.record()
+            torch.cuda.synchronize()
+            if r > 0:
+                ts.append(e0.elapsed_time(e1))
+            if r < 3:
+                qt.close()
+        ts.sort()
+        N = A0.shape[1]
+        X = torch.zeros_like(A0)
+        X[:N] = torch.triu(R)
+        qt.apply_q(X)
+        be = (torch.linalg.norm(X - A0) / torch.linalg.norm(A0)).item()
+        qt.close()
+        del X, A
+        torch.cuda.empty_cache()
+        return ts[len(ts) // 2], signed(R), be
+
+    for N, seed, blocks in ((16384, None, (1024, 4096, 16384)), (4096, 11, (64,))):
+        A_np = workloads.cfg3(N) if seed is None else workloads.gaussian(N, N, seed)
+        A0 = torch.from_numpy(A_np).cuda()
+        del A_np
+        fl = 4.0 * N ** 3 / 3.0
+        ms_r, R_r, be_r = timed(A0, lambda A: tq.caqr(A, panel=64, update=torch.float64))
+        row = {"right_looking": {"ms": round(ms_r, 2), "tflops": round(fl / ms_r / 1e9, 2), "backward_error": be_r}}
+        for w in blocks:
+            print("bench: caqr_left %d^2 blocks of %d" % (N, w), file=sys.stderr, flush=True)
+            ms, R, be = timed(A0, lambda A: tq.caqr_left(A, panel=64, block_cols=w, update=torch.float64))
+            dr = (torch.linalg.norm(R - R_r) / torch.linalg.norm(R_r)).item()
+            row["block_%d" % w] = {"ms": round(ms, 2), "tflops": round(fl / ms / 1e9, 2), "backward_error": be,
+                                   "R_diff_vs_right_looking": dr}
+            del R
+        res["%dx%d" % (N, N)] = row
+        del A0, R_r
+        torch.cuda.empty_cache()
     return res
 
 

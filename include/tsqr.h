@@ -312,6 +312,26 @@ int tsqr_plan_geometry(int64_t m, int64_t n, const tsqr_opts* opts, int64_t* out
 int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int update_dtype,
                 const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
 
+/* Left-looking CAQR over column blocks (Sec. 3.2: left-looking QR with TSQR
+ * panels has the same costs as the right-looking form).  The columns are cut
+ * into blocks of block_cols; block k first receives the implicit Q^T of
+ * every panel factored before it, oldest first (each panel's leaves, then
+ * its tree), and the panels inside the block are then factored and applied
+ * right-looking to the block's later columns.  Each column thus receives the
+ * same panel transformations in the same order as in caqr_factor; the
+ * results agree with caqr_factor's to rounding (the apply kernels chosen for
+ * a launch depend on its column count).  block_cols = panel is plain
+ * left-looking, block_cols >= n right-looking without look-ahead.  Panel
+ * trees: chains of eight 64-row blocks unless opts sets `chains`, combined
+ * node by node.  Every kernel runs on `stream`, one after the other.
+ *   dtype, m, n, A, lda, panel, update_dtype, opts, q_out: as caqr_factor
+ *   (same output layout and implicit Q).
+ *   block_cols: multiple of the panel width (0 = the panel width).
+ *   Errors: 1 dtype, 2 m, 3 n, 4 A, 5 lda, 6 panel, 7 block_cols,
+ *   8 update_dtype, 9 opts. */
+int caqr_factor_left(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int64_t block_cols,
+                     int update_dtype, const tsqr_opts* opts, tsqr_qtree* q_out, void* stream);
+
 /* D = sign(diag R) with sign(0) = +1; R <- D R and Q <- Q D, so diag(R) >= 0
  * (the QR factorisation is unique up to these signs, Sec. 2.1).
  * Q: device m x n (ldq >= n) or NULL; R: device n x n (ldr >= n). */

@@ -714,6 +714,87 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     return 0;
 }
 
+// Left-looking CAQR over column blocks (Sec. 3.2: left-looking QR with TSQR
+// panels has the costs of the right-looking form).  Column block k (w
+// columns) first receives the implicit Q^T of every panel factored before
+// it, oldest first (each application: the panel's leaves, then its tree);
+// inside the block the panels are right-looking.  Every column thus sees the
+// same panel transformations in the same order as in caqr_factor; w = panel
+// is plain left-looking, w >= n plain right-looking without look-ahead.
+// Everything runs on the caller's stream.
+int caqr_factor_left(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t panel, int64_t block_cols,
+                     int update_dtype, const tsqr_opts* opts, tsqr_qtree* q_out, void* stream) {
+    if (!check_dtype(dtype)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return n > m ? -2 : -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (panel == 0) panel = 64;
+    if (panel < 1 || panel > TSQR_MAX_N) return -6;
+    if (block_cols == 0) block_cols = panel;
+    if (block_cols < panel || block_cols % panel != 0) return -7;
+    if (!check_dtype(update_dtype)) return -8;
+    if (update_dtype == TSQR_F64 && dtype == TSQR_F32) return -8;
+    if (opts && (opts->flags & ~TSQR_FLAGS_ALL)) return -9;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = dtype == TSQR_F64;
+    const bool cf64 = update_dtype == TSQR_F64;
+    const size_t es = f64 ? 8 : 4;
+    tsqr_qtree_s* q = new tsqr_qtree_s();
+    q->kind = 1;
+    q->f64 = f64;
+    q->A = A;
+    q->lda = lda;
+    q->stream = st;
+    q->m = m;
+    q->n = n;
+    q->panel = panel;
+    // panel trees node by node (no wave waits on another), chains of eight
+    // 64-row blocks unless opts sets the chain count
+    auto factor_panel = [&](int64_t r0) -> int {
+        const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
+        const int64_t rows = m - r0;
+        char* P = (char*)A + ((size_t)r0 * lda + r0) * es;
+        tsqr_opts po = opts ? *opts : tsqr_opts{0, 0, 0, 0, 0};
+        if (po.chains == 0) {
+            const int64_t w = ((rows + 63) / 64 + 7) / 8;
+            po.chains = (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
+        }
+        po.flags |= TSQR_FLAG_TREE_LEVELWISE;
+        tsqr_qtree_s* pq = nullptr;
+        int rc = factor_impl(dtype, rows, cols, P, lda, P, lda, true, &po, &pq, st, true, 0);
+        if (rc != 0) return rc == -1 ? -2 : rc;
+        q->panels.push_back(pq);
+        return 0;
+    };
+    // Q^T of panel j (rows j*panel .. m-1) on `cols` columns from column c0
+    auto apply_panel = [&](size_t j, int64_t c0, int64_t cols) -> int {
+        tsqr_qtree_s* pq = q->panels[j];
+        char* B = (char*)A + ((size_t)j * panel * lda + c0) * es;
+        hipError_t e = tsqr::launch_apply(f64, cf64, pq->g, pq->A, pq->lda, pq->wk, B, lda, cols, tsqr::MODE_QT, st);
+        return e == hipSuccess ? 0 : hip_fail(e);
+    };
+    int rc = 0;
+    for (int64_t c0 = 0; rc == 0 && c0 < n; c0 += block_cols) {
+        const int64_t wc = (n - c0) < block_cols ? (n - c0) : block_cols;
+        const size_t before = q->panels.size();
+        for (size_t j = 0; rc == 0 && j < before; ++j) rc = apply_panel(j, c0, wc);
+        for (int64_t r0 = c0; rc == 0 && r0 < c0 + wc; r0 += panel) {
+            rc = factor_panel(r0);
+            const int64_t cols = (n - r0) < panel ? (n - r0) : panel;
+            const int64_t tc = c0 + wc - r0 - cols;
+            if (rc == 0 && tc > 0) rc = apply_panel(q->panels.size() - 1, r0 + cols, tc);
+        }
+    }
+    if (rc != 0) {
+        destroy_impl(q);
+        return rc;
+    }
+    if (q_out) *q_out = q;
+    else destroy_impl(q);
+    return 0;
+}
+
 int tsqr_qtree_destroy(tsqr_qtree q) {
     destroy_impl(q);
     return 0;

@@ -272,6 +272,22 @@ def caqr(A: torch.Tensor, panel: int = 64, update=None, block_rows=0, chains=0, 
     return R, QTree(h, A, m, n)
 
 
+def caqr_left(A: torch.Tensor, panel: int = 64, block_cols: int = 0, update=None, chains=0):
+    """Left-looking CAQR of A (m x n, m >= n) over column blocks of
+    `block_cols` columns (0 = the panel width: plain left-looking), IN
+    PLACE; same output layout and implicit Q as caqr.  Returns (R, QTree)."""
+    lib = _lib.load()
+    m, n = A.shape
+    upd = _dtype_code(A) if update is None else (_lib.TSQR_F64 if update == torch.float64 else _lib.TSQR_F32)
+    h = ctypes.c_void_p()
+    rc = lib.caqr_factor_left(_dtype_code(A), m, n, _ptr(A), _ld(A), panel, block_cols, upd,
+                              _opts(0, chains, 0, 0), ctypes.byref(h), _stream(A))
+    _lib.check("caqr_factor_left", rc)
+    R = torch.empty(n, n, dtype=A.dtype, device=A.device)
+    _lib.check("tsqr_copy_r", lib.tsqr_copy_r(_dtype_code(A), n, _ptr(A), _ld(A), _ptr(R), _ld(R), _stream(A)))
+    return R, QTree(h, A, m, n)
+
+
 def qr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
     """Thin QR with diag(R) >= 0; A is not modified.  Returns (Q, R)."""
     W = A.contiguous().clone()

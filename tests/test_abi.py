@@ -227,3 +227,25 @@ def test_noalloc_argument_errors_without_launch():
     big = _lib.opts(chains=4096)  # 4096 chain R slots of 64 x 64 FP64 exceed the fixed scratch
     assert g(1, 1 << 20, 64, f, 64, f, 64, ctypes.byref(big), None) == _lib.TSQR_ERR_SCRATCH
     assert lib.tsqr_factor_noalloc_scratch_bytes() == 40 << 20
+
+
+def test_caqr_left_argument_errors_without_launch():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: every call below fails its checks first
+    h = vp()
+    f = lib.caqr_factor_left
+    F64, F32 = _lib.TSQR_F64, _lib.TSQR_F32
+    assert f(7, 100, 50, fake, 50, 64, 64, F64, None, ctypes.byref(h), None) == -1     # dtype
+    assert f(F64, 0, 50, fake, 50, 64, 64, F64, None, ctypes.byref(h), None) == -2     # m
+    assert f(F64, 40, 50, fake, 50, 64, 64, F64, None, ctypes.byref(h), None) == -2    # m < n
+    assert f(F64, 100, 0, fake, 50, 64, 64, F64, None, ctypes.byref(h), None) == -3    # n
+    assert f(F64, 100, 50, None, 50, 64, 64, F64, None, ctypes.byref(h), None) == -4   # A
+    assert f(F64, 100, 50, fake, 49, 64, 64, F64, None, ctypes.byref(h), None) == -5   # lda
+    assert f(F64, 100, 50, fake, 50, 65, 65, F64, None, ctypes.byref(h), None) == -6   # panel > 64
+    assert f(F64, 100, 50, fake, 50, 64, 100, F64, None, ctypes.byref(h), None) == -7  # not a multiple
+    assert f(F64, 100, 50, fake, 50, 64, 32, F64, None, ctypes.byref(h), None) == -7   # below the panel
+    assert f(F32, 100, 50, fake, 50, 64, 64, F64, None, ctypes.byref(h), None) == -8   # FP64 update, FP32 storage
+    assert f(F64, 100, 50, fake, 50, 64, 64, 9, None, ctypes.byref(h), None) == -8     # update dtype
+    bad = _lib.opts(flags=64)  # not a defined flag
+    assert f(F64, 100, 50, fake, 50, 64, 64, F64, ctypes.byref(bad), ctypes.byref(h), None) == -9
