@@ -280,6 +280,19 @@ int tsqr_apply_q(tsqr_qtree q, int64_t k, void* B, int64_t ldb, void* stream);
  * n columns).  Errors: 1 q, 2 Q, 3 ldq. */
 int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream);
 
+/* The explicit thin Q with diag(R) made non-negative (the QR factorisation
+ * is unique up to the signs of R's rows and Q's columns, Sec. 2.1): Q <- Q D
+ * and R <- D R with D = diag(d), d_j = -1 where R_jj < 0, else +1, for every
+ * member of the implicit Q.  For TSQR (tsqr_factor, tsqr_factor_batched)
+ * the explicit-Q pass starts each member's tree from D instead of I_n, so Q D
+ * costs no pass of its own; the result is bit for bit that of tsqr_form_q
+ * followed by tsqr_sign_normalize(_batched).  For CAQR it is those two calls.
+ *   Q: device m x n (ldq >= n), written.  R: device, member b's n x n R at
+ *   R + b*strideR (ldr >= n; strideR >= n*ldr when there are several
+ *   members), read for D, then its rows scaled in stream order.
+ *   Errors: 1 q, 2 Q, 3 ldq, 4 R, 5 ldr, 6 strideR. */
+int tsqr_form_q_signed(tsqr_qtree q, void* Q, int64_t ldq, void* R, int64_t ldr, int64_t strideR, void* stream);
+
 /* Release the implicit Q (device workspace freed stream-ordered on the
  * stream of its creation).  NULL is accepted. */
 int tsqr_qtree_destroy(tsqr_qtree q);

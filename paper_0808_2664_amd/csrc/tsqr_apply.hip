@@ -1056,7 +1056,8 @@ __global__ __launch_bounds__(64 * TW, 1) void k_node_apply_w(Geom g, int lev, in
 template <typename S, typename C, int TW>
 __global__ __launch_bounds__(64 * TW, 2) void k_formq_paths_w(Geom g, int ngroups, S* __restrict__ B, int64_t ldb,
                                                               int64_t k, const S* __restrict__ Ynode,
-                                                              const S* __restrict__ Tnode) {
+                                                              const S* __restrict__ Tnode, const S* __restrict__ sgnR,
+                                                              int64_t sgn_ldr, int64_t sgn_sr) {
     constexpr int NT = 64 * TW, YS = 64 / TW, TSN = (W_TRI + NT - 1) / NT;
     typedef Mfma<C> M;
     typedef typename M::acc acc_t;
@@ -1069,12 +1070,16 @@ __global__ __launch_bounds__(64 * TW, 2) void k_formq_paths_w(Geom g, int ngroup
     auto xrow = [&](int kk) { return 16 * (kk >> 2) + M::orow(l4, kk & 3); };
     const int c1 = 2 * node1;
     if (c1 >= g.W) return;
-    // the member's root slab: I_n
+    // the member's root slab: I_n, or D = diag(sign R_jj) (sign(0) = +1);
+    // D's entries are +-1, so every later step gives the bits of I_n's
+    // result with column j negated where d_j = -1
+    S dcol = S(1);
+    if (sgnR && colok && sgnR[(int64_t)(c1 / g.cpm) * sgn_sr + col * sgn_ldr + col] < S(0)) dcol = S(-1);
     SAcc<S, C> sl[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sl[p][i] = (16 * p + M::orow(l4, i) == col) ? S(1) : S(0);
+        for (int i = 0; i < 4; ++i) sl[p][i] = (16 * p + M::orow(l4, i) == col) ? dcol : S(0);
     bool staged = false;
     for (int lev = g.levels; lev >= 1; --lev) {
         const int64_t stride = ipow(2, lev - 1), span = 2 * stride;
@@ -1175,11 +1180,15 @@ __global__ void k_apply_zero(int* __restrict__ p, int64_t count) {
 }
 
 template <typename T>
-__global__ void k_init_formq(int64_t n, int64_t mb, T* __restrict__ Q, int64_t ldq) {
+__global__ void k_init_formq(int64_t n, int64_t mb, T* __restrict__ Q, int64_t ldq, const T* __restrict__ sgnR,
+                             int64_t sgn_ldr, int64_t sgn_sr) {
+    // member blockIdx.y's root slab: I_n, or D = diag(sign R_jj) (sign(0) = +1)
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     const int64_t i = e / n, j = e - i * n;
-    Q[((int64_t)blockIdx.y * mb + i) * ldq + j] = (i == j) ? T(1) : T(0);
+    T d = T(1);
+    if (i == j && sgnR && sgnR[(int64_t)blockIdx.y * sgn_sr + j * sgn_ldr + j] < T(0)) d = T(-1);
+    Q[((int64_t)blockIdx.y * mb + i) * ldq + j] = (i == j) ? d : T(0);
 }
 
 // Layout of an apply with n = 64: the wide kernels (a 16-column tile over all
@@ -1351,7 +1360,8 @@ static hipError_t apply_mode(const Geom& g, const S* Y, int64_t ldy, const Work&
                 const int64_t gw = (int64_t)((g.W + 1) / 2) * ngroups;
                 if (gw > 0x7fffffff) return hipErrorInvalidValue;
                 k_formq_paths_w<S, C, 4><<<(unsigned)gw, 256, 0, st>>>(g, ngroups, B, ldb, k, (const S*)wk.Ynode,
-                                                                       (const S*)wk.Tnode);
+                                                                       (const S*)wk.Tnode, (const S*)wk.sgnR,
+                                                                       wk.sgn_ldr, wk.sgn_sr);
                 e = hipGetLastError();
                 done = true;
             }
@@ -1418,11 +1428,14 @@ hipError_t launch_fill_identity(bool f64, int64_t m, int64_t n, void* Q, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, hipStream_t st) {
+hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, const void* sgnR,
+                             int64_t sgn_ldr, int64_t sgn_sr, hipStream_t st) {
     if (members < 1 || members > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n * n + 255) / 256), (unsigned)members);
-    if (f64) k_init_formq<double><<<grid, 256, 0, st>>>(n, mb, (double*)Q, ldq);
-    else k_init_formq<float><<<grid, 256, 0, st>>>(n, mb, (float*)Q, ldq);
+    if (f64)
+        k_init_formq<double><<<grid, 256, 0, st>>>(n, mb, (double*)Q, ldq, (const double*)sgnR, sgn_ldr, sgn_sr);
+    else
+        k_init_formq<float><<<grid, 256, 0, st>>>(n, mb, (float*)Q, ldq, (const float*)sgnR, sgn_ldr, sgn_sr);
     return hipGetLastError();
 }
 

@@ -437,9 +437,36 @@ int tsqr_form_q(tsqr_qtree q, void* Q, int64_t ldq, void* stream) {
         if (e != hipSuccess) return hip_fail(e);
         return apply_impl(q, q->n, Q, ldq, tsqr::MODE_Q, st);
     }
-    hipError_t e = tsqr::launch_init_formq(q->f64, q->members, q->m / q->members, q->n, Q, ldq, st);
+    hipError_t e = tsqr::launch_init_formq(q->f64, q->members, q->m / q->members, q->n, Q, ldq, nullptr, 0, 0, st);
     if (e != hipSuccess) return hip_fail(e);
     return apply_one(q, q->n, Q, ldq, tsqr::MODE_FORMQ, q->f64, st);
+}
+
+int tsqr_form_q_signed(tsqr_qtree q, void* Q, int64_t ldq, void* R, int64_t ldr, int64_t strideR, void* stream) {
+    if (!q) return -1;
+    if (!Q) return -2;
+    if (ldq < q->n) return -3;
+    if (!R) return -4;
+    if (ldr < q->n) return -5;
+    if (q->members > 1 && strideR < q->n * ldr) return -6;
+    hipStream_t st = (hipStream_t)stream;
+    const int dt = q->f64 ? TSQR_F64 : TSQR_F32;
+    if (q->kind != 0) {
+        // CAQR: the explicit Q, then the signs in a pass of their own
+        int rc = tsqr_form_q(q, Q, ldq, stream);
+        return rc != 0 ? rc : tsqr_sign_normalize(dt, q->m, q->n, Q, ldq, R, ldr, stream);
+    }
+    // the root slab of each member starts as D = diag(sign R_jj): Q D in the
+    // explicit-Q pass itself (D is +-1, so the bits are those of Q, column j
+    // negated where d_j = -1); R's rows afterwards, in stream order
+    tsqr::Work wk = q->wk;
+    wk.sgnR = R;
+    wk.sgn_ldr = ldr;
+    wk.sgn_sr = strideR;
+    hipError_t e = tsqr::launch_init_formq(q->f64, q->members, q->m / q->members, q->n, Q, ldq, R, ldr, strideR, st);
+    if (e == hipSuccess) e = tsqr::launch_apply(q->f64, q->f64, q->g, q->A, q->lda, wk, Q, ldq, q->n, tsqr::MODE_FORMQ, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return tsqr_sign_normalize_batched(dt, q->members, 0, q->n, nullptr, q->n, R, ldr, strideR, stream);
 }
 
 // CAQR's split of the device between its two streams: the panel

@@ -86,6 +86,10 @@ struct Work {
     void* Tnode = nullptr;     // W x n(n+1)/2
     void* tau_node = nullptr;  // W x n
     int* cnt = nullptr;        // W x levels node arrival counters
+    // explicit Q with signs: when set, the root slab of member b starts as
+    // D_b = diag(sign of R_b's diagonal) instead of I_n (R_b at sgnR + b*sgn_sr)
+    const void* sgnR = nullptr;
+    int64_t sgn_ldr = 0, sgn_sr = 0;
 };
 
 enum ApplyMode { MODE_QT = 0, MODE_Q = 1, MODE_FORMQ = 2 };
@@ -135,7 +139,8 @@ hipError_t launch_copy_r(bool f64, int64_t n, const void* Rsrc, int64_t lds, voi
 hipError_t launch_apply(bool store_f64, bool compute_f64, const Geom& g, const void* Y, int64_t ldy,
                         const Work& wk, void* B, int64_t ldb, int64_t k, int mode, hipStream_t st);
 // [I_n; 0] at the top of every member's thin Q (the slab of each member's root chain).
-hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, hipStream_t st);
+hipError_t launch_init_formq(bool f64, int64_t members, int64_t mb, int64_t n, void* Q, int64_t ldq, const void* sgnR,
+                             int64_t sgn_ldr, int64_t sgn_sr, hipStream_t st);
 // Whether launch_apply takes the wide kernels (a 16-column tile of B over all
 // 64 rows of a block per wave) for k columns on geometry g.
 bool apply_wide(const Geom& g, int64_t k);

@@ -121,6 +121,18 @@ class QTree:
         _lib.check("tsqr_form_q", _lib.load().tsqr_form_q(self._h, _ptr(Q), _ld(Q), _stream(Q)))
         return Q
 
+    def form_q_signed(self, R: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Explicit thin Q with the signs of diag(R) folded in: Q <- Q D and
+        R <- D R (in place), D = diag(sign R_jj), in the explicit-Q pass
+        itself.  R: n x n, or members x n x n for a batched factorisation."""
+        Q = out if out is not None else torch.empty(self.m, self.n, dtype=self.dtype, device=self.device)
+        if R.dtype != self.dtype or R.device != self.device or R.size(-1) != self.n or R.stride(-1) != 1:
+            raise ValueError("R must be the factor's n x n R (or a batch of them)")
+        sr = R.stride(0) if R.dim() == 3 else 0
+        _lib.check("tsqr_form_q_signed", _lib.load().tsqr_form_q_signed(
+            self._h, _ptr(Q), _ld(Q), _ptr(R), R.stride(-2), sr, _stream(Q)))
+        return Q
+
     def close(self):
         if self._h is not None:
             _lib.load().tsqr_qtree_destroy(self._h)
@@ -292,8 +304,7 @@ def qr(A: torch.Tensor, block_rows=0, chains=0, arity=0):
     """Thin QR with diag(R) >= 0; A is not modified.  Returns (Q, R)."""
     W = A.contiguous().clone()
     R, qt = factor(W, block_rows=block_rows, chains=chains, arity=arity)
-    Q = qt.form_q()
-    sign_normalize(Q, R)
+    Q = qt.form_q_signed(R)
     qt.close()
     return Q, R
 
@@ -331,9 +342,8 @@ class TSQRFunction(torch.autograd.Function):
             # every member's explicit Q in one pass
             W = As.clone()
             R, qt = factor_batched(W, chains=chains, arity=arity)
-            Q = qt.form_q()
+            Q = qt.form_q_signed(R)
             qt.close()
-            sign_normalize_batched(Q, R)
             Q = Q.view(As.shape)
         else:
             Q, R = qr(As, block_rows=block_rows, chains=chains, arity=arity)

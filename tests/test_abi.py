@@ -249,3 +249,9 @@ def test_caqr_left_argument_errors_without_launch():
     assert f(F64, 100, 50, fake, 50, 64, 64, 9, None, ctypes.byref(h), None) == -8     # update dtype
     bad = _lib.opts(flags=64)  # not a defined flag
     assert f(F64, 100, 50, fake, 50, 64, 64, F64, ctypes.byref(bad), ctypes.byref(h), None) == -9
+
+
+def test_form_q_signed_argument_errors_without_launch():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.tsqr_form_q_signed(None, fake, 64, fake, 64, 0, None) == -1
