@@ -386,9 +386,21 @@ int tsqr_set_phase_events(int phase, void* start, void* stop);
  * on every device where it made them, after waiting for their work; a later
  * caqr_factor makes them again.  For callers that want no library-held
  * stream left at process exit (the Python binding calls it from an exit
- * handler).  Not to be called while a caqr_factor is running.  Errors:
+ * handler), and for callers that go on to other GPU work after their CAQR
+ * calls: while the masked streams exist, work on the process's other streams
+ * was measured to run slower (a TSQR step 2.08 against 1.79 ms).  Not to be
+ * called while a caqr_factor is running.  Errors:
  * TSQR_ERR_HIP. */
 int tsqr_release_streams(void);
+
+/* Workspaces (the implicit Q's, and the short-lived ones of the apply, least
+ * squares, CholeskyQR, MGS and adjoint calls) come from a stream-ordered
+ * memory pool of the library on each device, which keeps up to 2 GiB of freed
+ * memory cached across synchronisations so that repeated calls do not map
+ * their workspaces again.  This returns every pool's cached memory to the
+ * device (hipMemPoolTrimTo); memory still in use is unaffected.  No HIP call
+ * is made when no pool exists.  Errors: TSQR_ERR_HIP. */
+int tsqr_release_workspace_pools(void);
 
 /* Last HIP error code seen by this thread (0 if none) and a message. */
 int tsqr_last_hip_error(void);

@@ -87,6 +87,7 @@ def load():
         "tsqr_factor_noalloc": [i32, i64, i64, vp, i64, vp, i64, popts, vp],
         "tsqr_set_phase_events": [i32, vp, vp],
         "caqr_factor": [i32, i64, i64, vp, i64, i64, i32, popts, ctypes.POINTER(vp), vp],
+        "tsqr_release_workspace_pools": [],
         "tsqr_form_q_signed": [vp, vp, i64, vp, i64, i64, vp],
         "caqr_factor_left": [i32, i64, i64, vp, i64, i64, i64, i32, popts, ctypes.POINTER(vp), vp],
         "tsqr_copy_r": [i32, i64, vp, i64, vp, i64, vp],
@@ -116,6 +117,7 @@ def _release_at_exit():
     if _lib is not None:
         try:
             _lib.tsqr_release_streams()
+            _lib.tsqr_release_workspace_pools()
         except Exception:
             pass
 

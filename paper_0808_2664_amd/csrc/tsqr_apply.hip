@@ -1246,7 +1246,7 @@ static hipError_t qt_tree_launch(const Geom& g, const Work& wk, S* B, int64_t ld
     const int64_t nodes = (g.W + g.arity - 1) / g.arity;
     int* cnt = nullptr;
     const int64_t ncnt = (int64_t)g.W * (g.levels > 1 ? g.levels - 1 : 1) * ntiles;
-    hipError_t e = hipMallocAsync((void**)&cnt, (size_t)ncnt * sizeof(int), st);
+    hipError_t e = ws_malloc((void**)&cnt, (size_t)ncnt * sizeof(int), st);
     if (e != hipSuccess) return e;
     k_apply_zero<<<(unsigned)((ncnt + 255) / 256), 256, 0, st>>>(cnt, ncnt);
     const S *Yn = (const S*)wk.Ynode, *Tn = (const S*)wk.Tnode;

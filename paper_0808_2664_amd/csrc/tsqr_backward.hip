@@ -368,7 +368,7 @@ static hipError_t cholqr_nc(int64_t m, int n, const T* A, int64_t lda, T* Q, int
     const int64_t nch = (m + CR - 1) / CR;
     const size_t bytes = (size_t)(nch + 1 + 2) * NCP * NCP * sizeof(T);
     void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, bytes, st);
+    hipError_t e = ws_malloc(&ws, bytes, st);
     if (e != hipSuccess) return e;
     T* part = (T*)ws;
     T* G = part + (size_t)nch * NCP * NCP;
@@ -418,7 +418,7 @@ static hipError_t backward_nc(int64_t batch, int64_t m, int n, const T* Q, int64
     const size_t es = sizeof(T);
     const size_t bytes = (size_t)batch * (nch + 1 + 2) * NCP * NCP * es;
     void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, bytes, st);
+    hipError_t e = ws_malloc(&ws, bytes, st);
     if (e != hipSuccess) return e;
     T* part = (T*)ws;
     T* G = part + (size_t)batch * nch * NCP * NCP;

@@ -35,6 +35,59 @@ PhaseEvents g_phase;
 // launch) is launched.
 static std::atomic<bool> g_coop_seen{false};
 void note_cooperative_launch() { g_coop_seen.store(true, std::memory_order_relaxed); }
+
+// One workspace pool per device, made on first use; if the pool cannot be
+// made, the device's default pool serves.
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pool[64];
+static bool g_pool_tried[64];
+
+static hipMemPool_t device_pool(int dev) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_pool_tried[dev]) {
+        g_pool_tried[dev] = true;
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t keep = kPoolKeepBytes;
+            if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess) {
+                g_pool[dev] = pool;
+            } else {
+                (void)hipMemPoolDestroy(pool);
+            }
+        }
+        (void)hipGetLastError();
+    }
+    return g_pool[dev];
+}
+
+hipError_t ws_malloc(void** p, size_t bytes, hipStream_t st) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = (dev >= 0 && dev < 64) ? device_pool(dev) : nullptr;
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, st) : hipMallocAsync(p, bytes, st);
+}
+}
+
+extern "C" int tsqr_release_workspace_pools(void) {
+    std::lock_guard<std::mutex> lock(tsqr::g_pool_mu);
+    hipError_t first = hipSuccess;
+    for (int dev = 0; dev < 64; ++dev)
+        if (tsqr::g_pool[dev]) {
+            hipError_t e = hipMemPoolTrimTo(tsqr::g_pool[dev], 0);
+            if (e != hipSuccess && first == hipSuccess) first = e;
+        }
+    if (first != hipSuccess) {
+        g_last_hip = (int)first;
+        return TSQR_ERR_HIP;
+    }
+    return 0;
 }
 
 static int hip_fail(hipError_t e) {
@@ -242,7 +295,7 @@ static int factor_geom(int dtype, const Geom& g, void* A, int64_t lda, void* R, 
     q->n = n;
     q->members = g.m / g.mb;
     q->wk.bytes = tsqr::work_bytes(g, f64);
-    hipError_t e = hipMallocAsync(&q->wk.base, q->wk.bytes, st);
+    hipError_t e = tsqr::ws_malloc(&q->wk.base, q->wk.bytes, st);
     if (e != hipSuccess) {
         delete q;
         return hip_fail(e);
@@ -362,7 +415,7 @@ int tsqr_lstsq(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t k,
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = dtype == TSQR_F64;
     void* R = nullptr;
-    hipError_t e = hipMallocAsync(&R, (size_t)(n * n) * (f64 ? 8 : 4), st);
+    hipError_t e = tsqr::ws_malloc(&R, (size_t)(n * n) * (f64 ? 8 : 4), st);
     if (e != hipSuccess) return hip_fail(e);
     tsqr_qtree_s* q = nullptr;
     // without right-hand sides only R is needed (no implicit Q is formed)

@@ -127,6 +127,12 @@ constexpr int kDefaultMaxPolls = 1 << 22;
 // Device address of the library's status word on the current device (bit 0:
 // a bounded wait gave up), or null if it could not be obtained.
 int* status_word();
+// Stream-ordered workspace allocation from the library's memory pool on the
+// current device, which keeps up to kPoolKeepBytes of freed memory cached
+// across synchronisations (the default pool returns it at every one, so each
+// call would map its workspace again on the host).  Free with hipFreeAsync.
+constexpr uint64_t kPoolKeepBytes = 2ull << 30;
+hipError_t ws_malloc(void** p, size_t bytes, hipStream_t st);
 int make_geom_opts(int64_t m, int64_t n, const GeomOpts& o, Geom* g);
 size_t work_bytes(const Geom& g, bool f64);
 void work_carve(Work* w, const Geom& g, bool f64);

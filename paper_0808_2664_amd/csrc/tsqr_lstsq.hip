@@ -136,7 +136,7 @@ hipError_t launch_colnorm(bool f64, int64_t r0, int64_t m, const void* B, int64_
     if (nchunks < 1) nchunks = 1;
     const int64_t rows = (len + nchunks - 1) / nchunks;
     double* part = nullptr;
-    hipError_t e = hipMallocAsync((void**)&part, (size_t)(nchunks * k) * sizeof(double), st);
+    hipError_t e = ws_malloc((void**)&part, (size_t)(nchunks * k) * sizeof(double), st);
     if (e != hipSuccess) return e;
     const int cw = (k <= 32) ? 32 : 64;
     const dim3 grid((unsigned)((k + cw - 1) / cw), (unsigned)nchunks);

@@ -121,7 +121,7 @@ hipError_t mgs_t(int64_t m, int n, const T* A, int64_t lda, T* Q, int64_t ldq, T
     const int64_t nchunks = (m + kMgsRows - 1) / kMgsRows;
     if (nchunks > 0x7fffffff) return hipErrorInvalidValue;
     void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, (size_t)(nchunks * 64 + 128) * sizeof(T), st);
+    hipError_t e = ws_malloc(&ws, (size_t)(nchunks * 64 + 128) * sizeof(T), st);
     if (e != hipSuccess) return e;
     T* part = (T*)ws;
     T* coef = part + nchunks * 64;

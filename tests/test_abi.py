@@ -255,3 +255,8 @@ def test_form_q_signed_argument_errors_without_launch():
     lib = _lib.load()
     fake = ctypes.c_void_p(0x1000)
     assert lib.tsqr_form_q_signed(None, fake, 64, fake, 64, 0, None) == -1
+
+
+def test_release_workspace_pools_without_device_work():
+    # no pool exists before any call that allocates: no HIP call is made
+    assert _lib.load().tsqr_release_workspace_pools() == 0
