@@ -649,7 +649,9 @@ int caqr_factor(int dtype, int64_t m, int64_t n, void* A, int64_t lda, int64_t p
     // the switch point to the split device (below), in trailing columns
     // (16384^2: 8192 with the FP64 update, 12288 with FP32 products; the
     // whole run split loses 4 ms and gains 8, none split loses 7 and 8;
-    // 8192^2: split throughout is best)
+    // 8192^2: split throughout is best; with the pipelined panel trees on
+    // the masked stream, 6144 / 10240 (FP64) and 10240 / 14336 (FP32) were
+    // slower again)
     const int64_t split_cols = cf64 ? 8192 : 12288;
     // early: a panel factored before the switch point (whether or not the
     // device is then split, so that both schedules factor the same trees)
