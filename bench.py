@@ -174,12 +174,11 @@ def main():
     m, n, k = a.m, a.n, a.k
     extras = {}
     if not a.no_extras:
-        # CAQR first, in the state a process that runs only CAQR is in: once a
-        # process has made the cooperative launch of TSQR's pipelined tree,
-        # the library keeps CAQR on one shared device (no CU split).
+        # CAQR first (a process's first large allocations and the CU-masked
+        # streams it makes), then the TSQR step on the caller's stream
         print("bench: caqr", file=sys.stderr, flush=True)
         extras["caqr"] = bench_caqr(tq, torch, np, reps=max(1, a.caqr_reps))
-        extras["caqr"]["schedule"] = "measured before any cooperative TSQR launch in the process (CU split)"
+        extras["caqr"]["schedule"] = "CU split between panels and updates from 8192 (FP64) / 12288 (FP32) trailing columns"
         print("bench: caqr_left", file=sys.stderr, flush=True)
         extras["caqr_left"] = bench_caqr_left(tq, torch, np)
         # CAQR's CU-masked streams and the workspace pool's cached memory are

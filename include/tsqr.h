@@ -96,11 +96,8 @@ typedef struct tsqr_qtree_s* tsqr_qtree;
  *                (two chain workgroups of the first panel per unit) and its
  *                trailing updates on the other units, through two CU-masked
  *                streams of its own that it keeps until the process ends;
- *                with this flag both always run on every unit.  A process
- *                whose first caqr_factor comes after a tsqr_factor that may
- *                take the panel-pipelined tree (a cooperative launch) runs
- *                every caqr_factor on every unit too (there the split was
- *                slower than no split).  Same bits either way.
+ *                with this flag both always run on every unit.  Same bits
+ *                either way.
  *   max_polls  : in the panel-by-panel tree a wave waits for its children's
  *                progress, polling at most this many times (default 2^22,
  *                far beyond any real wait).  A wave that gives up sets the

@@ -3,7 +3,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -31,10 +30,6 @@ static thread_local int g_last_hip = 0;
 
 namespace tsqr {
 PhaseEvents g_phase;
-// Set before a factorisation that may take the pipelined tree (a cooperative
-// launch) is launched.
-static std::atomic<bool> g_coop_seen{false};
-void note_cooperative_launch() { g_coop_seen.store(true, std::memory_order_relaxed); }
 
 // One workspace pool per device, made on first use; if the pool cannot be
 // made, the device's default pool serves.
@@ -301,7 +296,6 @@ static int factor_geom(int dtype, const Geom& g, void* A, int64_t lda, void* R, 
         return hip_fail(e);
     }
     tsqr::work_carve(&q->wk, g, f64);
-    if (g.W > 1 && g.arity == 2 && !(g.flags & tsqr::TREE_LEVELWISE)) tsqr::note_cooperative_launch();
     e = tsqr::launch_factor(f64, g, A, lda, q->wk, R, ldr, rstride, !r_upper_only, want_q, opts ? opts->max_polls : 0,
                             st);
     if (e != hipSuccess) {
@@ -531,12 +525,8 @@ int tsqr_form_q_signed(tsqr_qtree q, void* Q, int64_t ldq, void* R, int64_t ldr,
 // stream's CU mask selects a CU of XCD i mod 8 (read back from the XCC_ID
 // register of the workgroups of masked streams): bits 0 .. 8r - 1 give r CUs
 // on every XCD, and every XCD keeps CUs in both masks.  The streams are made
-// once per device and r and kept until the process ends.  Not in a process
-// that made a cooperative launch (the pipelined tree of tsqr_factor) before
-// they existed: there the split ran CAQR slower than one shared device
-// (16384^2 FP64 update: 311 against 268 ms shared, 261 split in a process
-// without that launch; also with the pair made ahead of the launch, or made
-// per call), so such a process keeps every kernel on every unit.
+// once per device and r and kept until the process ends (or
+// tsqr_release_streams).
 constexpr int kSplitMaxR = 4;
 static std::mutex g_split_mu;
 static hipStream_t g_split_cache[64][kSplitMaxR][2];
@@ -552,7 +542,6 @@ static bool caqr_split_streams(int r, hipStream_t* upd, hipStream_t* fac) {
     std::lock_guard<std::mutex> lock(g_split_mu);
     if (!tried[dev][r - 1]) {
         tried[dev][r - 1] = true;
-        if (tsqr::g_coop_seen.load(std::memory_order_relaxed)) return false;
         int cus = 0;
         hipDeviceProp_t prop;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

@@ -16,8 +16,17 @@ struct WaveOcc {
     static constexpr int value = sizeof(T) == 8 ? 1 : 2;
 };
 
-// PIPE: the panel-pipelined binary tree; launched cooperatively, so that
-// every wave is resident and a node's wave may wait for its children.
+// PIPE: the panel-pipelined binary tree, where a node's wave waits for its
+// children's panels.  It is launched only when the device can hold all its
+// waves at once (one 64-lane workgroup per chain), with an ordinary launch:
+// with the device otherwise idle every workgroup is dispatched at once, and
+// workgroups held back by other work on the device are dispatched as that
+// work retires (it never waits on this kernel), so every wait ends; a wait
+// that does not end within TreeArgs::max_polls sets the status word
+// (TSQR_ERR_TIMEOUT) instead of hanging.  A cooperative launch would only
+// add the runtime's own co-residency check, and in a process that had made
+// one, later rocprofv3 exits faulted and CAQR on CU-masked streams ran
+// slower.
 // CHAIN = false: the chains were reduced by the two-wave chain kernel, whose
 // R factors are in Rbuf; this launch runs the tree only.
 template <typename T, int NP, int SG, bool PIPE, bool WQ, bool CHAIN>
@@ -57,22 +66,14 @@ template <typename T, int NP, int SG, bool WQ, bool CHAIN>
 static hipError_t launch_tree(const Geom& g, T* A, int64_t lda, const Work& wk, const TreeArgs& ta, hipStream_t st) {
     T *tau_blk = (T*)wk.tau_blk, *T_blk = (T*)wk.T_blk, *Rbuf = (T*)wk.Rbuf;
     T *Ynode = (T*)wk.Ynode, *Tnode = (T*)wk.Tnode, *tau_node = (T*)wk.tau_node;
-    const bool plain = (g.flags & TREE_PIPE_PLAIN) != 0;
-    if (plain && g.W > 1 && g.arity == 2) {
+    // TREE_PIPE_PLAIN: the caller has checked the residency on its own units
+    const bool pipe = g.W > 1 && g.arity == 2 &&
+                      ((g.flags & TREE_PIPE_PLAIN) ||
+                       (!(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ, CHAIN>()));
+    if (pipe) {
         k_wave_tsqr<T, NP, SG, true, WQ, CHAIN><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode,
                                                                     tau_node, ta);
         return hipGetLastError();
-    }
-    const bool pipe =
-        g.W > 1 && g.arity == 2 && !(g.flags & TREE_LEVELWISE) && g.W <= pipe_capacity<T, NP, SG, WQ, CHAIN>();
-    if (pipe) {
-        Geom gg = g;
-        TreeArgs tt = ta;
-        void* args[] = {&gg, &A, &lda, &tau_blk, &T_blk, &Rbuf, &Ynode, &Tnode, &tau_node, &tt};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_wave_tsqr<T, NP, SG, true, WQ, CHAIN>, dim3(g.W),
-                                                  dim3(64), args, 0, st);
-        if (e == hipSuccess) return hipSuccess;
-        (void)hipGetLastError();  // not co-resident after all: reduce level by level
     }
     k_wave_tsqr<T, NP, SG, false, WQ, CHAIN><<<g.W, 64, 0, st>>>(g, A, lda, tau_blk, T_blk, Rbuf, Ynode, Tnode,
                                                                  tau_node, ta);

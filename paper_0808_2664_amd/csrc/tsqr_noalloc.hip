@@ -19,10 +19,6 @@
 #include "../../include/tsqr.h"
 #include "tsqr_common.hpp"
 
-namespace tsqr {
-void note_cooperative_launch();  // tsqr_capi.hip
-}
-
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)40 << 20;  // 40 MiB per device
@@ -103,7 +99,6 @@ int tsqr_factor_noalloc(int dtype, int64_t m, int64_t n, void* A, int64_t lda, v
     // an implicit Q (the kernel is instantiated without them); their pointers
     // are set to valid memory all the same
     wk.tau_blk = wk.T_blk = wk.Ynode = wk.Tnode = wk.tau_node = base;
-    if (g.W > 1 && g.arity == 2 && !(g.flags & tsqr::TREE_LEVELWISE)) tsqr::note_cooperative_launch();
     e = tsqr::launch_factor(f64, g, A, lda, wk, R, ldr, 0, true, false, opts ? opts->max_polls : 0,
                             (hipStream_t)stream);
     return e == hipSuccess ? 0 : tsqr::record_hip_error(e);

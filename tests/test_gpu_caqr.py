@@ -191,8 +191,8 @@ def test_caqr_cu_split_same_bits():
     trailing columns are few, which here is from the first panel) and
     TSQR_FLAG_SHARED_CUS (every kernel on every CU) give the same bits: the
     reflectors and R in A, for the FP64 update and FP32 products, and R
-    agrees with the oracle.  In a fresh process: one that has already made a
-    cooperative launch (an earlier TSQR test) keeps CAQR on every CU."""
+    agrees with the oracle.  In a fresh process, so that the masked streams
+    are made by this check."""
     import os
     import subprocess
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
