@@ -392,3 +392,39 @@ def test_apply_qt_and_form_q_concurrent_streams():
     YRo, tauo = oracle.geqrf(A)
     np.testing.assert_allclose(np.linalg.norm(B1[:n].cpu().numpy(), axis=0),
                                np.linalg.norm(oracle.apply_qt(YRo, tauo, B)[:n], axis=0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("m,n,chains,dt", [(1 << 20, 64, 0, "f64"), (300000, 32, 1024, "f32")])
+def test_pipelined_tree_beside_concurrent_work(m, n, chains, dt):
+    """The panel-pipelined tree is an ordinary launch whose waves all fit on
+    the device.  With another stream keeping the device busy (large FP32
+    matmuls issued first), workgroups of the tree that cannot start at once
+    start as that work retires, so every wait ends: the same bits as a run on
+    an idle device, and no bounded wait gave up."""
+    import paper_0808_2664_amd as tq
+    _note("case: pipelined tree beside concurrent work m=%d n=%d %s" % (m, n, dt))
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    A_np = workloads.gaussian(m, n, 31)
+    A = _dev(A_np, dtype)
+    R0, qt = tq.factor(A, chains=chains)
+    Q0 = qt.form_q()
+    torch.cuda.synchronize()
+    qt.close()
+    assert tq.check_status() == 0
+    X = torch.randn(8192, 8192, device="cuda")
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    for _ in range(2):
+        A = _dev(A_np, dtype)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            Y = X
+            for _ in range(6):
+                Y = torch.mm(Y, X) * 1e-3
+        R, qt = tq.factor(A, chains=chains)
+        Q = qt.form_q()
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        qt.close()
+        assert tq.check_status() == 0
+        assert torch.equal(R, R0) and torch.equal(Q, Q0)
