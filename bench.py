@@ -547,6 +547,7 @@ def bench_fwd_bwd(tq, torch, np):
         Ag = A.clone().requires_grad_(True)
 
         def fwd_bwd():
+            Ag.grad = None  # each call computes dA afresh (no accumulation into the last call's)
             Q, R = tq.tsqr(Ag)
             torch.autograd.backward((Q, R), (dQ, dR))
         for f in (fwd, fwd_bwd):

@@ -176,7 +176,12 @@ __global__ __launch_bounds__(256) void k_adjoint_small(int n, const T* __restric
 }
 
 // dA = dQ Y + Q X over 256-row blocks (4 waves x 64 rows).
-template <typename T, int NC>
+// VEC (n a multiple of 16 and rows of dQ and Q aligned to 16 bytes): each
+// lane reads four consecutive entries of its row per load group (columns
+// 16h + 4 l4 .. +3), so a wave's load covers 16 rows in runs of 64 (FP32) or
+// 128 (FP64) bytes instead of 16 or 32; the K order of the products follows
+// (step 4h + j takes column 16h + 4 l4 + j), a permutation of the same sum.
+template <typename T, int NC, bool VEC>
 __global__ __launch_bounds__(256) void k_adjoint_stream(int64_t m, int n, const T* __restrict__ dQ, int64_t lddq,
                                                         int64_t sdq, const T* __restrict__ Q, int64_t ldq,
                                                         int64_t sq, const T* __restrict__ XY, T* __restrict__ dA,
@@ -205,20 +210,43 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(int64_t m, int n, const 
     for (int s = 0; s < 4; ++s) {
         const int64_t rr = base + 16 * s + l16;  // A-operand row of this lane
         T adq[NK], aq[NK];
+        if constexpr (VEC) {
+            typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+            constexpr int PER = 16 / (int)sizeof(T);  // entries of one 16-byte load
+            const bool ok = rr < m;
 #pragma unroll
-        for (int k4 = 0; k4 < NK; ++k4) {
-            const int cc = 4 * k4 + l4;
-            const bool ok = (rr < m) && (cc < n);
-            adq[k4] = (ok && dq) ? dq[rr * lddq + cc] : T(0);
-            aq[k4] = ok ? q[rr * ldq + cc] : T(0);
+            for (int h = 0; h < NP; ++h)
+#pragma unroll
+                for (int v = 0; v < 4 / PER; ++v) {
+                    const int cc = 16 * h + 4 * l4 + PER * v;
+                    const V z = V{};
+                    const V a = (ok && dq) ? *(const V*)(dq + rr * lddq + cc) : z;
+                    const V b = ok ? *(const V*)(q + rr * ldq + cc) : z;
+                    const T* pa = (const T*)&a;
+                    const T* pb = (const T*)&b;
+#pragma unroll
+                    for (int j = 0; j < PER; ++j) {
+                        adq[4 * h + PER * v + j] = pa[j];
+                        aq[4 * h + PER * v + j] = pb[j];
+                    }
+                }
+        } else {
+#pragma unroll
+            for (int k4 = 0; k4 < NK; ++k4) {
+                const int cc = 4 * k4 + l4;
+                const bool ok = (rr < m) && (cc < n);
+                adq[k4] = (ok && dq) ? dq[rr * lddq + cc] : T(0);
+                aq[k4] = ok ? q[rr * ldq + cc] : T(0);
+            }
         }
 #pragma unroll
         for (int c = 0; c < NP; ++c) {
             acc_t u = acc_t{0, 0, 0, 0};
 #pragma unroll
             for (int k4 = 0; k4 < NK; ++k4) {
-                u = M::mma(adq[k4], Ys[4 * k4 + l4][16 * c + l16], u);
-                u = M::mma(aq[k4], Xs[4 * k4 + l4][16 * c + l16], u);
+                const int kr = VEC ? 16 * (k4 >> 2) + 4 * l4 + (k4 & 3) : 4 * k4 + l4;
+                u = M::mma(adq[k4], Ys[kr][16 * c + l16], u);
+                u = M::mma(aq[k4], Xs[kr][16 * c + l16], u);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -428,8 +456,17 @@ static hipError_t backward_nc(int64_t batch, int64_t m, int n, const T* Q, int64
         k_gram_reduce<T, NC><<<dim3((NCP * NCP + 63) / 64, (unsigned)batch), 256, 0, st>>>((int)nch, part, G);
     }
     k_adjoint_small<T, NC><<<(unsigned)batch, 256, 0, st>>>(n, R, ldr, sr, dR, lddr, sdr, G, dQ ? 1 : 0, XY);
-    k_adjoint_stream<T, NC><<<dim3((unsigned)((m + 255) / 256), (unsigned)batch), 256, 0, st>>>(
-        m, n, dQ, lddq, sdq, Q, ldq, sq, XY, dA, ldda, sda);
+    // 16-byte loads: n fills the padded width, and every row start of dQ and
+    // Q (base, leading dimension, member stride) is 16-byte aligned
+    const int64_t al = 16 / (int64_t)es;
+    auto aligned = [&](const T* p, int64_t ld, int64_t s) {
+        return p == nullptr || (((uintptr_t)p % 16) == 0 && ld % al == 0 && (batch == 1 || s % al == 0));
+    };
+    const dim3 grid((unsigned)((m + 255) / 256), (unsigned)batch);
+    if (n == NCP && aligned(dQ, lddq, sdq) && aligned(Q, ldq, sq))
+        k_adjoint_stream<T, NC, true><<<grid, 256, 0, st>>>(m, n, dQ, lddq, sdq, Q, ldq, sq, XY, dA, ldda, sda);
+    else
+        k_adjoint_stream<T, NC, false><<<grid, 256, 0, st>>>(m, n, dQ, lddq, sdq, Q, ldq, sq, XY, dA, ldda, sda);
     e = hipGetLastError();
     hipError_t e2 = hipFreeAsync(ws, st);
     return e != hipSuccess ? e : e2;
