@@ -36,24 +36,42 @@ __global__ __launch_bounds__(256) void k_gram(int64_t m, int n, const T* __restr
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int c = 0; c < NP; ++c) acc[p][c] = acc_t{0, 0, 0, 0};
-    for (int64_t r0 = lo + 16 * wv; r0 < hi; r0 += 64) {
+    // a 64-row step's rows (4 per lane and column tile), loaded one step
+    // ahead of the products that use them; the products and their order are
+    // those of a plain loop over the steps
+    auto load_step = [&](int64_t r0, T (&a)[4][NP], T (&bq)[4][NP]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t r = r0 + M::orow(l4, i);
-            T a[NP], bq[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int cc = 16 * p + l16;
                 const bool ok = (r < hi) && (cc < n);
-                a[p] = ok ? dq[r * lddq + cc] : T(0);
-                bq[p] = SYM ? a[p] : (ok ? q[r * ldq + cc] : T(0));
+                a[i][p] = ok ? dq[r * lddq + cc] : T(0);
+                bq[i][p] = SYM ? a[i][p] : (ok ? q[r * ldq + cc] : T(0));
             }
+        }
+    };
+    T a[4][NP], bq[4][NP];
+    int64_t r0 = lo + 16 * wv;
+    if (r0 < hi) load_step(r0, a, bq);
+    for (; r0 < hi; r0 += 64) {
+        T na[4][NP], nb[4][NP];
+        if (r0 + 64 < hi) load_step(r0 + 64, na, nb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int c = 0; c < NP; ++c)
-                    if (!SYM || c >= p) acc[p][c] = M::mma(a[p], bq[c], acc[p][c]);
-        }
+                    if (!SYM || c >= p) acc[p][c] = M::mma(a[i][p], bq[i][c], acc[p][c]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                a[i][p] = na[i][p];
+                bq[i][p] = nb[i][p];
+            }
     }
     T* out = part + ((int64_t)b * nch + ch) * NCP * NCP;
 #pragma unroll
