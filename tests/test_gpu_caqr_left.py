@@ -107,3 +107,30 @@ def test_caqr_left_f32_storage():
     qt.close()
     _note("  R error %.2e, backward error %.2e" % (e, be))
     assert e <= 5e-4 and be <= 1e-5
+
+
+def test_caqr_left_4096_blocks_of_2048_both_updates():
+    """4096 x 4096 in column blocks of 2048: the earlier panels' Q^T reach the
+    second block through the wide apply kernels (asserted on the first panel's
+    tree: 8 chains x 32 column groups of 64);
+    the whole R against the oracle's blocked Householder QR, FP64 update and
+    FP32 products."""
+    import paper_0808_2664_amd as tq
+    N = 4096
+    A = workloads.gaussian(N, N, 960)
+    Ro = _oracle_r(A)
+    for upd in (torch.float64, torch.float32):
+        _note("case: caqr_left 4096^2 blocks of 2048, update %s" % upd)
+        Ad = _dev(A)
+        A_keep = Ad.clone()
+        R, qt = tq.caqr_left(Ad, panel=64, block_cols=2048, update=upd)
+        torch.cuda.synchronize()
+        assert qt.wide_layout(2048, panel=0)
+        e = oracle.rel_err(_signed(R), Ro)
+        be = _backward_error(qt, A_keep, R, N, N)
+        qt.close()
+        _note("  R error %.2e, backward error %.2e" % (e, be))
+        if upd == torch.float64:
+            assert e <= 1e-11 and be <= 1e-13
+        else:
+            assert 1e-12 < e <= 1e-4 and be <= 1e-4
